@@ -1,0 +1,233 @@
+/*
+ * filter2d.h -- C ABI of the MI355X (gfx950) K x K 2D filter library.
+ *
+ * The operation is the generalisation of the 3x3 Laplacian sharpen of
+ * arXiv:2504.01266 (Section 4.2.4, "Sharpening": every output pixel is a
+ * weighted sum of its neighbourhood, each colour channel on its own) to
+ *
+ *   Y[n][o][y][x] = sum_{i in inputs(o)} sum_{u,v=0}^{K-1}
+ *                   F[o|i][u][v] * X[n][i][cl_H(y+u-r)][cl_W(x+v-r)]
+ *
+ * with odd K, r = (K-1)/2, correlation (tap (u,v) weighs the neighbour at
+ * offset (u-r, v-r)) and clamp-to-edge borders cl_n(t) = min(max(t,0), n-1)
+ * applied to each axis.  Where the paper skips out-of-image neighbours
+ * (Section 4.2.4) this library clamps; zero borders are reserved.
+ *
+ * Channel modes (F is always a contiguous [f_out][f_in][k][k] array):
+ *   F2D_CH_SHARED     f_out = f_in = 1: the same filter on every channel
+ *                     (the paper's per-channel loop of Section 4.2.4).
+ *   F2D_CH_DEPTHWISE  f_in = 1, f_out = C*m: filter c*m+j is applied to
+ *                     channel c (m = 2 with Sobel-x / Sobel-y gives edge maps).
+ *   F2D_CH_BANK       f_in = C: output channel o sums the correlations of all
+ *                     C input channels i with F[o][i] (a convolution layer;
+ *                     K = 1, C = 3, f_out = 1 is the weighted RGB -> gray map
+ *                     of Section 4.2.5, "Grayscaling").
+ *
+ * Conventions for every entry point:
+ *   - Data pointers in f2d_tensor / f2d_filter / f2d_batch_item are DEVICE
+ *     pointers; every other pointer argument is a HOST pointer unless stated.
+ *   - The caller owns every buffer (images, filters, outputs, workspaces,
+ *     descriptor tables).  The library allocates no device memory, keeps no
+ *     device state between calls and never synchronises the stream, except in
+ *     the explicitly synchronous filter2d_autotune_* calls.
+ *   - `stream` is a hipStream_t (NULL = the default stream); work is only
+ *     enqueued on it, so calls are capturable into a hipGraph.
+ *   - Arguments are validated on the host before anything is enqueued: an
+ *     invalid call returns a non-zero status, enqueues nothing and leaves the
+ *     outputs untouched; filter2d_last_error() then names the argument.
+ *   - A launch failure returns F2D_EHIP with the HIP error text.  Faults that
+ *     happen while the kernels run are reported by the next synchronising
+ *     HIP call, as for any asynchronous launch.
+ *   - Strides are in ELEMENTS; the x (column) stride is always 1.
+ *   - Outputs must not overlap inputs.
+ */
+#ifndef FILTER2D_H
+#define FILTER2D_H
+
+#include <stddef.h>
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+typedef int32_t f2d_status;
+#define F2D_OK 0
+#define F2D_EINVAL 1       /* malformed argument (shape, stride, null pointer, even K ...) */
+#define F2D_EUNSUPPORTED 2 /* well-formed but not implemented (dtype combination, border ...) */
+#define F2D_EWORKSPACE 3   /* workspace missing or smaller than required */
+#define F2D_EHIP 4         /* the HIP runtime refused a launch */
+
+/* element types */
+#define F2D_U8 0
+#define F2D_I32 1
+#define F2D_F32 2
+#define F2D_BF16 3
+
+/* border rules */
+#define F2D_BORDER_CLAMP 0 /* replicate the edge pixel: cl_n(t) = min(max(t,0), n-1) */
+#define F2D_BORDER_ZERO 1  /* reserved: returns F2D_EUNSUPPORTED */
+
+/* channel modes */
+#define F2D_CH_SHARED 0
+#define F2D_CH_DEPTHWISE 1
+#define F2D_CH_BANK 2
+
+/* epilogues */
+#define F2D_EPI_NONE 0
+#define F2D_EPI_SUMSQ_PAIRS 1 /* DEPTHWISE m = 2 only: an extra output o0^2 + o1^2 */
+
+/* A 4-D image [n][c][h][w]. */
+typedef struct f2d_tensor {
+  void* data;      /* device pointer to element (0,0,0,0) */
+  int32_t dtype;   /* F2D_U8 / F2D_I32 / F2D_F32 / F2D_BF16 */
+  int32_t reserved;
+  int64_t n, c, h, w;
+  int64_t stride_n, stride_c, stride_h; /* elements */
+} f2d_tensor;
+
+/* A filter bank [f_out][f_in][k][k], contiguous. */
+typedef struct f2d_filter {
+  const void* data; /* device pointer */
+  int32_t dtype;    /* F2D_I32 (u8 images), F2D_F32, F2D_BF16 */
+  int32_t f_out, f_in, k;
+} f2d_filter;
+
+typedef struct f2d_opts {
+  int32_t border;   /* F2D_BORDER_CLAMP */
+  int32_t channels; /* F2D_CH_* */
+  int32_t epilogue; /* F2D_EPI_* */
+  int32_t variant;  /* 0: tuned / default tiling; > 0 forces a tiling variant */
+  /* Output rows [row_begin, row_end) of the INPUT buffer are produced
+   * (row_end <= 0 means image->h).  A GPU that owns output rows [y0, y1) of an
+   * image of height H passes the input rows [max(0,y0-r), min(H,y1+r)) as the
+   * image and selects its own rows here; clamping at the buffer edge then
+   * equals clamping at the image edge, so bands concatenate to the whole. */
+  int64_t row_begin, row_end;
+} f2d_opts;
+
+/*
+ * filter2d_forward -- Y = filter(X), the equation at the top of this file.
+ *
+ *   image   [N][C][H][W]
+ *   filter  see the channel modes
+ *   outs    n_outs output descriptors, each [N][C_o][rows][W] with
+ *           rows = row_end - row_begin:
+ *             SHARED     n_outs = 1, C_o = C
+ *             DEPTHWISE  n_outs = m (+1 with SUMSQ_PAIRS), C_o = C; outs[j]
+ *                        holds the response of filter c*m+j to channel c
+ *                        (pass strided views for an interleaved [N][C*m] layout)
+ *             BANK       n_outs = 1, C_o = f_out
+ *   dtypes  U8 image + I32 filter -> I32 outputs (SHARED, DEPTHWISE): exact
+ *           integer sums, wrapping modulo 2^32 if they leave the int32 range;
+ *           F32 + F32 -> F32 (all modes), FP32 accumulation;
+ *           BF16 + BF16 -> F32 or BF16 (BANK only), FP32 accumulation on the
+ *           matrix cores, output rounded to nearest even for BF16.
+ *   K       odd, 1 <= K <= 31 (F32, U8); K in {1,3,5,7,9} for BF16 banks.
+ */
+f2d_status filter2d_forward(const f2d_tensor* image, const f2d_filter* filter,
+                            const f2d_opts* opts, const f2d_tensor* outs, int32_t n_outs,
+                            void* stream);
+
+/*
+ * Workspace bytes that filter2d_backward needs for these arguments (device
+ * memory, caller-allocated, any alignment >= 256 bytes).  Returns 0 for
+ * invalid arguments.
+ */
+size_t filter2d_backward_workspace(const f2d_tensor* image, const f2d_filter* filter,
+                                   const f2d_opts* opts);
+
+/*
+ * filter2d_backward -- the adjoints of filter2d_forward (whole images only:
+ * opts->row_begin/row_end must select all rows).
+ *
+ *   grad_outs    n_grad_outs upstream gradients laid out like forward's outs
+ *                (no SUMSQ output); F32 (or BF16 for BF16 banks).
+ *   grad_input   nullable, [N][C][H][W] F32:  X-bar = A^T G-bar.  At the clamp
+ *                borders every edge pixel also receives the gradient of the
+ *                neighbours that were clamped onto it.
+ *   grad_filter  nullable, device, contiguous F32 [f_out][f_in][k][k]:
+ *                F-bar[o][i][u][v] = sum_{n,y,x} G-bar[n][o][y][x] *
+ *                X[n][i][cl(y+u-r)][cl(x+v-r)]  (summed over channels too in
+ *                SHARED mode), reduced in a fixed order, so repeated calls are
+ *                bitwise identical.
+ *   workspace    device scratch of filter2d_backward_workspace() bytes.
+ * U8 images are not differentiable (F2D_EUNSUPPORTED).
+ */
+f2d_status filter2d_backward(const f2d_tensor* image, const f2d_filter* filter,
+                             const f2d_tensor* grad_outs, int32_t n_grad_outs,
+                             const f2d_opts* opts, const f2d_tensor* grad_input,
+                             float* grad_filter, void* workspace, size_t workspace_bytes,
+                             void* stream);
+
+/*
+ * Ragged batches: images of different sizes, each with its own filter,
+ * filtered in ONE persistent launch (the batch processing the paper lists as
+ * missing in Section 5).  SHARED mode, F32, clamp-to-edge; every item uses
+ * the same K.
+ */
+typedef struct f2d_batch_item {
+  const void* image;  /* device [c][h][w] */
+  void* out;          /* device [c][h][w] */
+  const void* filter; /* device [k][k] */
+  int64_t c, h, w;
+  int64_t in_stride_c, in_stride_h, out_stride_c, out_stride_h; /* elements */
+} f2d_batch_item;
+
+/*
+ * Host-side plan: validates the items (host copies) and writes the tile prefix
+ * sum tile_prefix[0..n_items] (host array).  *variant selects the tiling
+ * (0 = tuned / default, replaced by the resolved variant on return); pass the
+ * same variant in opts->variant to filter2d_batched.  Returns the total
+ * number of tiles, or a negative f2d_status on error.
+ */
+int64_t filter2d_batched_plan(const f2d_batch_item* items, int32_t n_items, int32_t dtype,
+                              int32_t k, int32_t* variant, int64_t* tile_prefix);
+
+/*
+ * filter2d_batched -- one persistent launch over every tile of every item.
+ * items_dev and tile_prefix_dev are device copies of the plan's inputs and
+ * outputs.  The call reads nothing from them on the host, so it is safe to
+ * capture into a hipGraph and replay while the tables stay resident.
+ */
+f2d_status filter2d_batched(const f2d_batch_item* items_dev, const int64_t* tile_prefix_dev,
+                            int32_t n_items, int64_t total_tiles, int32_t dtype, int32_t k,
+                            const f2d_opts* opts, void* stream);
+
+/*
+ * Autotuner: times every tiling variant of the forward (resp. batched) call
+ * for these arguments `reps` times with HIP events on `stream`, records the
+ * fastest in the process-wide tuning table (keyed by path, dtype, K, channel
+ * mode and image-width class) and returns it in *best_variant.  These calls
+ * synchronise the stream and overwrite the outputs.
+ */
+f2d_status filter2d_autotune_forward(const f2d_tensor* image, const f2d_filter* filter,
+                                     const f2d_opts* opts, const f2d_tensor* outs,
+                                     int32_t n_outs, int32_t reps, void* stream,
+                                     int32_t* best_variant);
+f2d_status filter2d_autotune_batched(const f2d_batch_item* items_host,
+                                     const f2d_batch_item* items_dev, int32_t n_items,
+                                     int32_t dtype, int32_t k, int64_t* tile_prefix_dev,
+                                     int32_t reps, void* stream, int32_t* best_variant);
+
+/* Number of tiling variants of a path: 0 = forward F32, 1 = forward U8,
+ * 2 = batched F32 (variant numbers run 1..count). */
+int32_t filter2d_variant_count(int32_t path);
+
+/* Save / load the tuning table as JSON (host file).  Loading merges. */
+f2d_status filter2d_tune_save(const char* path);
+f2d_status filter2d_tune_load(const char* path);
+/* Drop every tuned entry (variant 0 then means the built-in default). */
+void filter2d_tune_clear(void);
+
+const char* filter2d_status_string(f2d_status s);
+/* Detail of the last non-OK status returned on this thread (host string). */
+const char* filter2d_last_error(void);
+/* Library version as major*10000 + minor*100 + patch. */
+int32_t filter2d_version(void);
+
+#ifdef __cplusplus
+}
+#endif
+
+#endif /* FILTER2D_H */

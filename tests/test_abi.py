@@ -1,0 +1,159 @@
+"""The C-ABI library: it loads, exports every symbol its header declares, and
+rejects malformed calls on the host before anything is enqueued.  No call
+here reaches a kernel, so these tests run without a GPU."""
+import ctypes
+import os
+import re
+import subprocess
+
+import pytest
+
+from paper_2504_01266_amd import binding as B
+
+ROOT = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
+HEADER = os.path.join(ROOT, "include", "filter2d.h")
+
+FAKE = 0x100000  # never dereferenced: validation fails before any device access
+
+
+def _declared():
+    text = open(HEADER).read()
+    return sorted(set(re.findall(r"\b(filter2d_\w+)\s*\(", text)))
+
+
+@pytest.fixture(scope="module")
+def lib():
+    if not os.path.exists(B.LIB_PATH):
+        pytest.skip("libfilter2d.so not built")
+    return B.load()
+
+
+def test_every_declared_symbol_is_exported(lib):
+    names = _declared()
+    assert len(names) >= 14
+    out = subprocess.run(["nm", "-D", "--defined-only", B.LIB_PATH], capture_output=True,
+                         text=True, check=True).stdout
+    exported = set(re.findall(r"\bT (filter2d_\w+)", out))
+    missing = [n for n in names if n not in exported]
+    assert not missing, missing
+    for n in names:
+        assert hasattr(lib, n)
+
+
+def test_struct_sizes_match_the_header(lib):
+    assert ctypes.sizeof(B.F2dTensor) == 72
+    assert ctypes.sizeof(B.F2dFilter) == 24
+    assert ctypes.sizeof(B.F2dOpts) == 32
+    assert ctypes.sizeof(B.F2dBatchItem) == 80
+
+
+def test_version_and_status_strings(lib):
+    assert lib.filter2d_version() >= 100
+    assert b"EINVAL" in lib.filter2d_status_string(B.EINVAL)
+    assert lib.filter2d_variant_count(B.PATH_F32) >= 1
+    assert lib.filter2d_variant_count(B.PATH_U8) >= 1
+    assert lib.filter2d_variant_count(99) == 0
+
+
+def _img(dtype=B.F32, n=1, c=3, h=32, w=40):
+    return B.F2dTensor(FAKE, dtype, 0, n, c, h, w, c * h * w, h * w, w)
+
+
+def _filt(k=3, f_out=1, f_in=1, dtype=B.F32):
+    return B.F2dFilter(FAKE, dtype, f_out, f_in, k)
+
+
+def _fwd(lib, image, filt, opts, outs):
+    arr = (B.F2dTensor * max(len(outs), 1))(*outs)
+    return lib.filter2d_forward(ctypes.byref(image), ctypes.byref(filt), ctypes.byref(opts), arr,
+                                len(outs), None)
+
+
+CASES = [
+    # (description, image, filter, opts, outs, expected status, message fragment)
+    ("even K", _img(), _filt(k=4), B.make_opts(), [_img()], B.EINVAL, "odd"),
+    ("K too large", _img(), _filt(k=33), B.make_opts(), [_img()], B.EINVAL, "odd"),
+    ("shared needs 1x1 filter", _img(), _filt(f_out=2), B.make_opts(), [_img()], B.EINVAL, "SHARED"),
+    ("depthwise f_out not multiple of C", _img(c=3), _filt(f_out=4), B.make_opts("depthwise"),
+     [_img()], B.EINVAL, "multiple"),
+    ("bank f_in != C", _img(c=3), _filt(f_out=4, f_in=2), B.make_opts("bank"), [_img()], B.EINVAL,
+     "f_in"),
+    ("zero border reserved", _img(), _filt(), B.F2dOpts(B.BORDER_ZERO, 0, 0, 0, 0, 0), [_img()],
+     B.EUNSUPPORTED, "reserved"),
+    ("unknown border", _img(), _filt(), B.F2dOpts(7, 0, 0, 0, 0, 0), [_img()], B.EINVAL, "border"),
+    ("wrong output count", _img(), _filt(), B.make_opts(), [_img(), _img()], B.EINVAL, "expected 1"),
+    ("wrong output shape", _img(), _filt(), B.make_opts(), [_img(h=31)], B.EINVAL, "shape"),
+    ("band outside image", _img(h=32), _filt(), B.make_opts(rows=(10, 40)), [_img(h=30)], B.EINVAL,
+     "outside"),
+    ("negative stride", _img(), _filt(), B.make_opts(),
+     [B.F2dTensor(FAKE, B.F32, 0, 1, 3, 32, 40, -1, 1280, 40)], B.EINVAL, "stride"),
+    ("null output data", _img(), _filt(), B.make_opts(),
+     [B.F2dTensor(None, B.F32, 0, 1, 3, 32, 40, 3840, 1280, 40)], B.EINVAL, "NULL"),
+    ("overlapping output rows", _img(), _filt(), B.make_opts(),
+     [B.F2dTensor(FAKE, B.F32, 0, 1, 3, 32, 40, 3840, 1280, 20)], B.EINVAL, "stride_h"),
+    ("u8 needs int32 filter", _img(B.U8), _filt(), B.make_opts(), [_img(B.I32)], B.EINVAL, "int32"),
+    ("u8 output must be int32", _img(B.U8), _filt(dtype=B.I32), B.make_opts(), [_img(B.F32)],
+     B.EINVAL, "dtype"),
+    ("sumsq needs depthwise m=2", _img(B.U8), _filt(dtype=B.I32),
+     B.make_opts("shared", B.EPI_SUMSQ_PAIRS), [_img(B.I32)], B.EINVAL, "SUMSQ"),
+    ("bf16 only for banks", _img(B.BF16), _filt(dtype=B.BF16), B.make_opts(), [_img()],
+     B.EUNSUPPORTED, "BANK"),
+    ("null filter data", _img(), B.F2dFilter(None, B.F32, 1, 1, 3), B.make_opts(), [_img()],
+     B.EINVAL, "NULL"),
+]
+
+
+@pytest.mark.parametrize("case", CASES, ids=[c[0] for c in CASES])
+def test_forward_rejects_on_the_host(lib, case):
+    _, image, filt, opts, outs, status, frag = case
+    assert _fwd(lib, image, filt, opts, outs) == status
+    assert frag.lower() in B.last_error().lower()
+
+
+def test_backward_validation_on_the_host(lib):
+    image, filt = _img(), _filt(k=3)
+    opts = B.make_opts()
+    g = (B.F2dTensor * 1)(_img())
+    # u8 images are not differentiable
+    st = lib.filter2d_backward(ctypes.byref(_img(B.U8)), ctypes.byref(_filt(dtype=B.I32)), g, 1,
+                               ctypes.byref(opts), None, None, None, 0, None)
+    assert st == B.EUNSUPPORTED
+    # bands are forward-only
+    st = lib.filter2d_backward(ctypes.byref(image), ctypes.byref(filt), g, 1,
+                               ctypes.byref(B.make_opts(rows=(0, 8))), None, None, None, 0, None)
+    assert st == B.EUNSUPPORTED
+    # even K
+    st = lib.filter2d_backward(ctypes.byref(image), ctypes.byref(_filt(k=2)), g, 1,
+                               ctypes.byref(opts), None, None, None, 0, None)
+    assert st == B.EINVAL
+    assert lib.filter2d_backward_workspace(ctypes.byref(image), ctypes.byref(_filt(k=2)),
+                                           ctypes.byref(opts)) == 0
+
+
+def test_batched_plan_validation_on_the_host(lib):
+    item = B.F2dBatchItem(FAKE, FAKE, FAKE, 3, 10, 12, 120, 12, 120, 12)
+    items = (B.F2dBatchItem * 2)(item, item)
+    prefix = (ctypes.c_int64 * 3)()
+    var = ctypes.c_int32(0)
+    assert lib.filter2d_batched_plan(items, 2, B.F32, 4, ctypes.byref(var), prefix) == -B.EINVAL
+    assert lib.filter2d_batched_plan(items, 2, B.U8, 3, ctypes.byref(var), prefix) == -B.EUNSUPPORTED
+    bad = B.F2dBatchItem(FAKE, FAKE, FAKE, 3, -1, 12, 120, 12, 120, 12)
+    items2 = (B.F2dBatchItem * 1)(bad)
+    assert lib.filter2d_batched_plan(items2, 1, B.F32, 3, ctypes.byref(var), prefix) == -B.EINVAL
+    total = lib.filter2d_batched_plan(items, 2, B.F32, 3, ctypes.byref(var), prefix)
+    assert total > 0 and var.value >= 1
+    assert prefix[0] == 0 and prefix[2] == total and prefix[1] == total // 2
+
+
+def test_tune_table_roundtrip(lib, tmp_path):
+    p = tmp_path / "tune.json"
+    lib.filter2d_tune_clear()
+    assert lib.filter2d_tune_save(str(p).encode()) == B.OK
+    assert '"entries"' in p.read_text()
+    p.write_text('{"format": "filter2d-tune-1", "entries": [[0, 2, 5, 0, 3, 2], [1, 0, 3, 1, 3, 4]]}')
+    assert lib.filter2d_tune_load(str(p).encode()) == B.OK
+    q = tmp_path / "tune2.json"
+    assert lib.filter2d_tune_save(str(q).encode()) == B.OK
+    assert "[0, 2, 5, 0, 3, 2]" in q.read_text() and "[1, 0, 3, 1, 3, 4]" in q.read_text()
+    lib.filter2d_tune_clear()
+    assert lib.filter2d_tune_load(b"/nonexistent/tune.json") == B.EINVAL
