@@ -76,14 +76,16 @@ f2d_status run_backward(const Problem& pr, const f2d_tensor* grad_outs, int32_t 
   if (n_grad_outs != want) return fail(F2D_EINVAL, "expected %d grad_outs, got %d", want, n_grad_outs);
   if (want > kMaxT) return fail(F2D_EUNSUPPORTED, "DEPTHWISE backward supports at most %d filters per channel", kMaxT);
   if (!grad_outs) return fail(F2D_EINVAL, "grad_outs is NULL");
-  const int32_t gdt = im.dtype;  // upstream gradients share the image's element type
+  // upstream gradients share the image's element type (bf16 banks also take f32)
+  const int32_t gdt = im.dtype;
   const int64_t co = pr.mode == F2D_CH_BANK ? pr.c_out : im.c;
   for (int32_t j = 0; j < n_grad_outs; ++j) {
     if (f2d_status e = check_tensor(&grad_outs[j], "grad_outs[j]", false)) return e;
     const f2d_tensor& g = grad_outs[j];
     if (g.n != im.n || g.c != co || g.h != im.h || g.w != im.w)
       return fail(F2D_EINVAL, "grad_outs[%d]: shape does not match the forward output", j);
-    if (g.dtype != gdt) return fail(F2D_EINVAL, "grad_outs[%d]: dtype %d, expected %d", j, g.dtype, gdt);
+    const bool ok_dt = g.dtype == gdt || (gdt == F2D_BF16 && g.dtype == F2D_F32);
+    if (!ok_dt) return fail(F2D_EINVAL, "grad_outs[%d]: dtype %d does not match the image", j, g.dtype);
   }
   if (grad_input) {
     if (f2d_status e = check_tensor(grad_input, "grad_input", true)) return e;
@@ -161,7 +163,7 @@ f2d_status run_backward(const Problem& pr, const f2d_tensor* grad_outs, int32_t 
     if (!templ) p.flags |= kFlip | kZeroBorder;
     hipError_t err = launch_stencil_f32(p, K, 1, true, templ ? 1 : -1, s);
     if (err != hipSuccess) return hip_status(err, "grad_input launch");
-    err = launch_grad_input_edges(e, F2D_F32, s);
+    err = launch_grad_input_edges(e, kEdgeF32, s);
     if (err != hipSuccess) return hip_status(err, "grad_input edge launch");
   }
 

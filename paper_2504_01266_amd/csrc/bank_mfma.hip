@@ -1,17 +1,610 @@
-// BF16 filter bank on the matrix cores: placeholder until the kernels land.
+// BF16 filter banks on the gfx950 matrix cores (FP32 accumulation).
+//
+// A bank Y[n][o] = sum_i corr(X[n][i], W[o][i]) is an implicit GEMM: for
+// every output pixel p, Y[o][p] = sum_k A[o][k] * B[k][p] with the
+// contraction index k = (tap (u,v), input channel i), A = the weights and
+// B = the K*K-neighbourhood of p (never materialised: it is read from an LDS
+// tile with its clamped halo).  k is ordered tap-major, channel-minor, so one
+// 8-element MFMA operand slice is 8 consecutive channels of one pixel, i.e.
+// 16 contiguous bytes of the channels-last LDS tile.
+//
+//  k_bank_conv   v_mfma_f32_16x16x32_bf16.  A persistent work-group keeps
+//                the whole weight matrix (all taps x channels of OT*16 output
+//                channels) in LDS and loops over 4 x (16*PT)-pixel tiles; each
+//                wave owns one tile row and OT x PT 16x16 accumulator blocks.
+//                Forward: clamp-to-edge borders.  Adjoint in the image
+//                (dgrad): zero borders and the transposed, flipped weights;
+//                the edge pixels are then recomputed exactly by the shared
+//                clamp-fold kernel.  Upstream gradients given in FP32 are
+//                rounded to BF16 (nearest even) while they are staged.
+//  k_bank_wgrad  W-bar[o][i][u][v] = sum_p G[o][p] * X[i][shift_uv(p)]: for
+//                every tap a 16(o) x 16(i) block contracted over 32-pixel
+//                steps; the shifted X operand is built from three aligned
+//                16-byte LDS reads per row and byte-aligned funnel shifts.
+//                Per-unit partials go to the workspace and are reduced in a
+//                fixed order.
+#include <hip/hip_bf16.h>
+#include <hip/hip_runtime.h>
+
+#include <cstring>
+#include <mutex>
+
 #include "f2d_host.hpp"
+#include "f2d_internal.hpp"
+#include "grad_internal.hpp"
 
 namespace f2d {
+namespace {
 
-f2d_status bank_forward_bf16(const Problem&, const f2d_tensor*, hipStream_t) {
-  return fail(F2D_EUNSUPPORTED, "bf16 banks are not implemented yet");
+typedef __bf16 bf16x8 __attribute__((ext_vector_type(8)));
+typedef float f32x4 __attribute__((ext_vector_type(4)));
+typedef uint32_t u32x4 __attribute__((ext_vector_type(4)));
+
+constexpr int kThreads = 256;
+constexpr int kWaves = 4;
+constexpr int kTH = 4;  // tile rows: one per wave
+
+struct BankParams {
+  const void* src;  // source planes: X (bf16) or, for the adjoint, G-bar (bf16 or f32)
+  int64_t s_sn, s_sc, s_sh;
+  void* dst;  // output planes (f32, or bf16 for a bf16 forward output)
+  int64_t d_sn, d_sc, d_sh;
+  const uint16_t* w;  // forward weights [fo][fi][K][K], bf16 bits
+  int64_t H, W, row0, rows;
+  int32_t CI, CO;  // channels of the source and of the output of THIS map
+  int32_t fo, fi;  // forward weight extents
+  int32_t tiles_x, tiles_y, o_groups;
+  int64_t n_tiles;  // N * o_groups * tiles_y * tiles_x
+};
+
+__device__ __forceinline__ uint16_t f32_to_bf16_bits(float f) {
+  // round to nearest even (NaN kept quiet)
+  uint32_t u = __float_as_uint(f);
+  if ((u & 0x7f800000u) == 0x7f800000u && (u & 0x7fffffu)) return static_cast<uint16_t>((u >> 16) | 0x40);
+  u += 0x7fffu + ((u >> 16) & 1u);
+  return static_cast<uint16_t>(u >> 16);
 }
 
-size_t bank_backward_bf16_workspace(const Problem&) { return 256; }
+template <typename TS>
+__device__ __forceinline__ uint16_t load_bits(const TS* p);
+template <>
+__device__ __forceinline__ uint16_t load_bits<uint16_t>(const uint16_t* p) {
+  return *p;
+}
+template <>
+__device__ __forceinline__ uint16_t load_bits<float>(const float* p) {
+  return f32_to_bf16_bits(*p);
+}
 
-f2d_status bank_backward_bf16(const Problem&, const f2d_tensor&, const f2d_tensor*, float*, void*, size_t,
-                              hipStream_t) {
-  return fail(F2D_EUNSUPPORTED, "bf16 banks are not implemented yet");
+template <int K, int OT, int PT, int CG>
+struct ConvGeom {
+  static constexpr int R = (K - 1) / 2;
+  static constexpr int CI8 = CG * 8;         // staged channels (padded)
+  static constexpr int KG = K * K * CG;      // 8-wide k-groups
+  static constexpr int STEPS = (KG + 3) / 4; // 32-wide MFMA steps
+  static constexpr int KP = STEPS * 32;
+  static constexpr int WSTR = KP + 8;        // weight row stride (elements), staggers banks
+  static constexpr int TW = 16 * PT;
+  static constexpr int LH = kTH + K - 1;
+  static constexpr int LW = TW + K - 1;
+  static constexpr int S_ELEMS = LH * LW * CI8 + 8;  // + one zero 16-byte slot
+  static constexpr int W_ELEMS = OT * 16 * WSTR;
+};
+
+template <int K, int OT, int PT, int CG, bool ADJ, typename TS, bool OUT_BF16>
+__global__ __launch_bounds__(kThreads) void k_bank_conv(BankParams p) {
+  using G = ConvGeom<K, OT, PT, CG>;
+  extern __shared__ uint4 smem4[];
+  uint16_t* wl = reinterpret_cast<uint16_t*>(smem4);
+  uint16_t* sl = wl + G::W_ELEMS;
+  const int tid = threadIdx.x;
+  const int lane = tid % 64, wave = tid / 64;
+  const int l16 = lane % 16, q = lane / 16;
+
+  const int64_t per_group = static_cast<int64_t>(p.tiles_x) * p.tiles_y;
+  int cur_og = -1;
+  for (int64_t t = blockIdx.x; t < p.n_tiles; t += gridDim.x) {
+    const int64_t ng = t / per_group;
+    const int64_t r = t - ng * per_group;
+    const int og = static_cast<int>(ng % p.o_groups);
+    const int64_t n = ng / p.o_groups;
+    const int64_t tile_y = r / p.tiles_x, tile_x = r - tile_y * p.tiles_x;
+    const int64_t oy0 = tile_y * kTH, ox0 = tile_x * G::TW;
+
+    // weights of this output group, [co_local][k] with k = (uv*CG + cg)*8 + c
+    if (og != cur_og) {
+      for (int idx = tid; idx < OT * 16 * G::KP; idx += kThreads) {
+        const int col = idx / G::KP, k = idx - col * G::KP;
+        const int co = og * OT * 16 + col;
+        const int gi = k / 8, ci = (gi % CG) * 8 + k % 8, uv = gi / CG;
+        uint16_t v = 0;
+        if (co < p.CO && gi < G::KG && ci < p.CI) {
+          const int u = uv / K, vv = uv % K;
+          if constexpr (ADJ)  // Wt[co][ci][u][v] = W[ci][co][K-1-u][K-1-v]
+            v = p.w[((static_cast<int64_t>(ci) * p.fi + co) * K + (K - 1 - u)) * K + (K - 1 - vv)];
+          else
+            v = p.w[((static_cast<int64_t>(co) * p.fi + ci) * K + u) * K + vv];
+        }
+        wl[col * G::WSTR + k] = v;
+      }
+      cur_og = og;
+    }
+    // source tile, channels-last, border rule by index arithmetic
+    const TS* sp = static_cast<const TS*>(p.src) + n * p.s_sn;
+    for (int idx = tid; idx < G::CI8 * G::LH * G::LW; idx += kThreads) {
+      const int ci = idx / (G::LH * G::LW);
+      const int rem = idx - ci * (G::LH * G::LW);
+      const int ly = rem / G::LW, lx = rem - ly * G::LW;
+      int64_t gy = p.row0 + oy0 - G::R + ly, gx = ox0 - G::R + lx;
+      uint16_t v = 0;
+      if (ci < p.CI) {
+        if constexpr (ADJ) {
+          if (gy >= 0 && gy < p.H && gx >= 0 && gx < p.W) v = load_bits<TS>(sp + ci * p.s_sc + gy * p.s_sh + gx);
+        } else {
+          gy = gy < 0 ? 0 : (gy >= p.H ? p.H - 1 : gy);
+          gx = gx < 0 ? 0 : (gx >= p.W ? p.W - 1 : gx);
+          v = load_bits<TS>(sp + ci * p.s_sc + gy * p.s_sh + gx);
+        }
+      }
+      sl[(ly * G::LW + lx) * G::CI8 + ci] = v;
+    }
+    if (tid < 8) sl[G::S_ELEMS - 8 + tid] = 0;
+    __syncthreads();
+
+    f32x4 acc[OT][PT];
+#pragma unroll
+    for (int a = 0; a < OT; ++a)
+#pragma unroll
+      for (int b = 0; b < PT; ++b) acc[a][b] = f32x4{0.f, 0.f, 0.f, 0.f};
+
+    for (int s = 0; s < G::STEPS; ++s) {
+      const int gi = 4 * s + q;
+      const int uv = gi / CG, cg = gi - (gi / CG) * CG;
+      const int u = uv / K, v = uv - (uv / K) * K;
+      bf16x8 af[OT], bfr[PT];
+#pragma unroll
+      for (int a = 0; a < OT; ++a)
+        af[a] = *reinterpret_cast<const bf16x8*>(wl + (a * 16 + l16) * G::WSTR + gi * 8);
+#pragma unroll
+      for (int b = 0; b < PT; ++b) {
+        const int off = gi < G::KG ? ((wave + u) * G::LW + b * 16 + l16 + v) * G::CI8 + cg * 8
+                                   : G::S_ELEMS - 8;
+        bfr[b] = *reinterpret_cast<const bf16x8*>(sl + off);
+      }
+#pragma unroll
+      for (int a = 0; a < OT; ++a)
+#pragma unroll
+        for (int b = 0; b < PT; ++b)
+          acc[a][b] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(af[a], bfr[b], acc[a][b], 0, 0, 0);
+    }
+
+    // D[o = 16a + 4q + j][pixel = 16b + l16]
+    const int64_t oy = oy0 + wave;
+    if (oy < p.rows) {
+#pragma unroll
+      for (int a = 0; a < OT; ++a)
+#pragma unroll
+        for (int j = 0; j < 4; ++j) {
+          const int co = og * OT * 16 + a * 16 + 4 * q + j;
+          if (co >= p.CO) continue;
+#pragma unroll
+          for (int b = 0; b < PT; ++b) {
+            const int64_t ox = ox0 + b * 16 + l16;
+            if (ox >= p.W) continue;
+            const int64_t o = n * p.d_sn + co * p.d_sc + oy * p.d_sh + ox;
+            if constexpr (OUT_BF16)
+              static_cast<uint16_t*>(p.dst)[o] = f32_to_bf16_bits(acc[a][b][j]);
+            else
+              static_cast<float*>(p.dst)[o] = acc[a][b][j];
+          }
+        }
+    }
+    __syncthreads();  // the next tile restages the LDS source tile
+  }
+}
+
+// ------------------------------------------------------------------ wgrad --
+
+constexpr int kWgTH = 8;   // rows per wgrad tile
+constexpr int kWgTW = 64;  // columns per wgrad tile (two 32-pixel steps)
+
+struct WgradParams {
+  const uint16_t* x;  // bf16 image
+  int64_t x_sn, x_sc, x_sh;
+  const void* g;  // upstream gradient (bf16 or f32)
+  int64_t g_sn, g_sc, g_sh;
+  float* partial;  // [unit][CO][CI][K*K]
+  int64_t H, W;
+  int32_t CI, CO;
+  int32_t tiles_x, tiles_y, tiles_per_unit, chunks;
+  int32_t o_groups, i_groups;
+  int64_t n_units;  // N * chunks
+};
+
+template <int K>
+struct WgGeom {
+  static constexpr int R = (K - 1) / 2;
+  static constexpr int LH = kWgTH + K - 1;
+  static constexpr int LWP = kWgTW + 16 + 8;  // columns x0-8 .. x0+TW+8, + 8 pad
+  static constexpr int ELEMS = 16 * LH * LWP;
+};
+
+__device__ __forceinline__ uint32_t funnel16(uint32_t hi, uint32_t lo) {
+  return __builtin_amdgcn_alignbit(hi, lo, 16);
+}
+
+// 8 consecutive bf16 starting at element E (0 <= E <= 16) of the 24-element
+// window held in w[0..11] (two bf16 per dword, little endian).
+template <int E>
+__device__ __forceinline__ bf16x8 window8(const uint32_t (&w)[12]) {
+  u32x4 r;
+  if constexpr (E % 2 == 0) {
+    r = u32x4{w[E / 2], w[E / 2 + 1], w[E / 2 + 2], w[E / 2 + 3]};
+  } else {
+    constexpr int d = E / 2;
+    r = u32x4{funnel16(w[d + 1], w[d]), funnel16(w[d + 2], w[d + 1]), funnel16(w[d + 3], w[d + 2]),
+              funnel16(w[d + 4], w[d + 3])};
+  }
+  return __builtin_bit_cast(bf16x8, r);
+}
+
+template <int K, int V>
+__device__ __forceinline__ void wg_taps(f32x4 (&acc)[K * K], int u, const bf16x8& a,
+                                        const uint32_t (&w)[12]) {
+  if constexpr (V < K) {
+    constexpr int R = (K - 1) / 2;
+    acc[u * K + V] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(a, window8<8 + V - R>(w), acc[u * K + V], 0, 0, 0);
+    wg_taps<K, V + 1>(acc, u, a, w);
+  }
+}
+
+template <int K, typename TG>
+__global__ __launch_bounds__(kThreads) void k_bank_wgrad(WgradParams p) {
+  using G = WgGeom<K>;
+  __shared__ uint4 xs4[(G::ELEMS + 7) / 8];
+  uint16_t* xs = reinterpret_cast<uint16_t*>(xs4);
+  const int tid = threadIdx.x, lane = tid % 64, wave = tid / 64;
+  const int l16 = lane % 16, q = lane / 16;
+
+  int64_t b = blockIdx.x;
+  const int ig = static_cast<int>(b % p.i_groups);
+  b /= p.i_groups;
+  const int ogp = static_cast<int>(b % p.o_groups);
+  const int64_t unit = b / p.o_groups;
+  const int64_t n = unit / p.chunks;
+  const int64_t chunk = unit - n * p.chunks;
+  const int o = ogp * 64 + wave * 16 + l16;   // A row of this lane
+  const int ci_b = ig * 16 + l16;             // B column of this lane
+  const uint16_t* xp = p.x + n * p.x_sn;
+  const TG* gp = static_cast<const TG*>(p.g) + n * p.g_sn;
+
+  f32x4 acc[K * K];
+#pragma unroll
+  for (int e = 0; e < K * K; ++e) acc[e] = f32x4{0.f, 0.f, 0.f, 0.f};
+
+  const int64_t tiles = static_cast<int64_t>(p.tiles_x) * p.tiles_y;
+  for (int tt = 0; tt < p.tiles_per_unit; ++tt) {
+    const int64_t tile = chunk * p.tiles_per_unit + tt;
+    if (tile >= tiles) break;
+    const int64_t y0 = (tile / p.tiles_x) * kWgTH, x0 = (tile % p.tiles_x) * kWgTW;
+    // X tile [ci][row][col], clamped; LDS column c <-> source column x0 - 8 + c
+    for (int idx = tid; idx < 16 * G::LH * (kWgTW + 16); idx += kThreads) {
+      const int c = idx / (G::LH * (kWgTW + 16));
+      const int rem = idx - c * (G::LH * (kWgTW + 16));
+      const int ly = rem / (kWgTW + 16), lx = rem - ly * (kWgTW + 16);
+      int64_t gy = y0 - G::R + ly, gx = x0 - 8 + lx;
+      gy = gy < 0 ? 0 : (gy >= p.H ? p.H - 1 : gy);
+      gx = gx < 0 ? 0 : (gx >= p.W ? p.W - 1 : gx);
+      const int ci = ig * 16 + c;
+      xs[(c * G::LH + ly) * G::LWP + lx] = ci < p.CI ? xp[ci * p.x_sc + gy * p.x_sh + gx] : 0;
+    }
+    __syncthreads();
+    for (int ry = 0; ry < kWgTH; ++ry) {
+      const int64_t y = y0 + ry;
+      if (y >= p.H) break;
+#pragma unroll
+      for (int ks = 0; ks < kWgTW / 32; ++ks) {
+        const int64_t xb = x0 + ks * 32 + 8 * q;  // first of this lane's 8 pixels
+        // A: G-bar[o][y][xb..xb+7], zero outside the image or past C_out
+        uint32_t ab[4];
+#pragma unroll
+        for (int d = 0; d < 4; ++d) {
+          uint32_t lo = 0, hi = 0;
+          if (o < p.CO) {
+            const TG* row = gp + o * p.g_sc + y * p.g_sh;
+            if (xb + 2 * d < p.W) lo = load_bits<TG>(row + xb + 2 * d);
+            if (xb + 2 * d + 1 < p.W) hi = load_bits<TG>(row + xb + 2 * d + 1);
+          }
+          ab[d] = lo | (hi << 16);
+        }
+        const bf16x8 a = __builtin_bit_cast(bf16x8, u32x4{ab[0], ab[1], ab[2], ab[3]});
+#pragma unroll
+        for (int u = 0; u < K; ++u) {
+          // LDS row ry+u of channel l16; columns ks*32 + 8q + {0..23}
+          const uint32_t* rw = reinterpret_cast<const uint32_t*>(
+              xs + (l16 * G::LH + ry + u) * G::LWP + ks * 32 + 8 * q);
+          uint32_t w[12];
+#pragma unroll
+          for (int c = 0; c < 3; ++c) {
+            const u32x4 t4 = *reinterpret_cast<const u32x4*>(rw + 4 * c);
+            w[4 * c + 0] = t4.x;
+            w[4 * c + 1] = t4.y;
+            w[4 * c + 2] = t4.z;
+            w[4 * c + 3] = t4.w;
+          }
+          wg_taps<K, 0>(acc, u, a, w);
+        }
+      }
+    }
+    __syncthreads();
+  }
+  // D[o = ogp*64 + wave*16 + 4q + j][ci = ig*16 + l16]
+  const int ci = ig * 16 + l16;
+#pragma unroll
+  for (int j = 0; j < 4; ++j) {
+    const int oo = ogp * 64 + wave * 16 + 4 * q + j;
+    if (oo >= p.CO || ci >= p.CI) continue;
+    float* dst = p.partial + ((unit * p.CO + oo) * p.CI + ci) * (K * K);
+#pragma unroll
+    for (int e = 0; e < K * K; ++e) dst[e] = acc[e][j];
+  }
+  (void)ci_b;
+}
+
+// ------------------------------------------------------------- dispatch --
+
+template <int K, int OT, int PT, int CG, bool ADJ, typename TS, bool OB>
+hipError_t conv_go(const BankParams& p, hipStream_t s) {
+  using G = ConvGeom<K, OT, PT, CG>;
+  const size_t lds = static_cast<size_t>(G::W_ELEMS + G::S_ELEMS) * 2;
+  if (lds > 160 * 1024) return hipErrorInvalidValue;
+  static std::mutex mu;
+  static int dev_cached = -1, grid_cached = 0;
+  int dev = 0;
+  hipError_t e = hipGetDevice(&dev);
+  if (e != hipSuccess) return e;
+  int grid;
+  {
+    std::lock_guard<std::mutex> lk(mu);
+    if (dev_cached != dev) {
+      auto kern = k_bank_conv<K, OT, PT, CG, ADJ, TS, OB>;
+      e = hipFuncSetAttribute(reinterpret_cast<const void*>(kern), hipFuncAttributeMaxDynamicSharedMemorySize,
+                              static_cast<int>(lds));
+      if (e != hipSuccess) return e;
+      int per_cu = 0, cus = 0;
+      e = hipOccupancyMaxActiveBlocksPerMultiprocessor(&per_cu, kern, kThreads, lds);
+      if (e != hipSuccess) return e;
+      e = hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, dev);
+      if (e != hipSuccess) return e;
+      grid_cached = (per_cu > 0 ? per_cu : 1) * (cus > 0 ? cus : 1);
+      dev_cached = dev;
+    }
+    grid = grid_cached;
+  }
+  const int64_t g = p.n_tiles < grid ? p.n_tiles : grid;
+  if (g <= 0) return hipSuccess;
+  hipLaunchKernelGGL((k_bank_conv<K, OT, PT, CG, ADJ, TS, OB>), dim3(static_cast<uint32_t>(g)), dim3(kThreads),
+                     lds, s, p);
+  return hipGetLastError();
+}
+
+template <int K, bool ADJ, typename TS, bool OB>
+hipError_t conv_by_shape(const BankParams& p, int ot, int cg, hipStream_t s) {
+  // instantiated (OT, CG) pairs, PT = 4 (64-pixel tile rows); the adjoint's
+  // outputs are the forward's input channels (<= 16, one tile)
+  if constexpr (!ADJ) {
+    if (ot == 4 && cg == 2) return conv_go<K, 4, 4, 2, ADJ, TS, OB>(p, s);
+    if (ot == 4 && cg == 1) return conv_go<K, 4, 4, 1, ADJ, TS, OB>(p, s);
+    if (ot == 4 && cg == 4) return conv_go<K, 4, 4, 4, ADJ, TS, OB>(p, s);
+    if (ot == 2 && cg == 1) return conv_go<K, 2, 4, 1, ADJ, TS, OB>(p, s);
+    if (ot == 2 && cg == 2) return conv_go<K, 2, 4, 2, ADJ, TS, OB>(p, s);
+    if (ot == 2 && cg == 8) return conv_go<K, 2, 4, 8, ADJ, TS, OB>(p, s);
+    if (ot == 1 && cg == 1) return conv_go<K, 1, 4, 1, ADJ, TS, OB>(p, s);
+    if (ot == 1 && cg == 2) return conv_go<K, 1, 4, 2, ADJ, TS, OB>(p, s);
+  } else {
+    if (ot == 1 && cg == 8) return conv_go<K, 1, 4, 8, ADJ, TS, OB>(p, s);
+    if (ot == 1 && cg == 4) return conv_go<K, 1, 4, 4, ADJ, TS, OB>(p, s);
+    if (ot == 1 && cg == 2) return conv_go<K, 1, 4, 2, ADJ, TS, OB>(p, s);
+    if (ot == 1 && cg == 1) return conv_go<K, 1, 4, 1, ADJ, TS, OB>(p, s);
+  }
+  return hipErrorNotSupported;
+}
+
+template <bool ADJ, typename TS, bool OB>
+hipError_t conv_by_k(const BankParams& p, int K, int ot, int cg, hipStream_t s) {
+  switch (K) {
+    case 1: return conv_by_shape<1, ADJ, TS, OB>(p, ot, cg, s);
+    case 3: return conv_by_shape<3, ADJ, TS, OB>(p, ot, cg, s);
+    case 5: return conv_by_shape<5, ADJ, TS, OB>(p, ot, cg, s);
+    default: return hipErrorNotSupported;
+  }
+}
+
+// output-channel tiles per work-group and channel groups of 8 for a map
+// with ci source and co output channels
+bool conv_shape(int64_t ci, int64_t co, int* ot, int* cg) {
+  const int64_t g8 = (ci + 7) / 8;
+  if (g8 > 8) return false;
+  *cg = g8 <= 1 ? 1 : (g8 <= 2 ? 2 : (g8 <= 4 ? 4 : 8));
+  *ot = co <= 16 ? 1 : (co <= 32 ? 2 : 4);
+  if (*cg == 8 && *ot == 4) *ot = 2;  // keep the weights within LDS
+  return true;
+}
+
+size_t wgrad_bytes(const Problem& pr, int64_t* chunks, int* tpu, int32_t* tx, int32_t* ty) {
+  const f2d_tensor& im = pr.image;
+  *tx = static_cast<int32_t>((im.w + kWgTW - 1) / kWgTW);
+  *ty = static_cast<int32_t>((im.h + kWgTH - 1) / kWgTH);
+  const int64_t tiles = static_cast<int64_t>(*tx) * *ty;
+  int64_t t = tiles * im.n / 2048;  // aim at >= ~2048 work-groups
+  t = t < 1 ? 1 : (t > 32 ? 32 : t);
+  *tpu = static_cast<int>(t);
+  *chunks = (tiles + t - 1) / t;
+  return static_cast<size_t>(im.n * *chunks) * pr.c_out * im.c * pr.k * pr.k * sizeof(float);
+}
+
+}  // namespace
+
+f2d_status bank_forward_bf16(const Problem& pr, const f2d_tensor* outs, hipStream_t s) {
+  const f2d_tensor& im = pr.image;
+  const f2d_tensor& out = outs[0];
+  int ot, cg;
+  if (!conv_shape(im.c, pr.c_out, &ot, &cg))
+    return fail(F2D_EUNSUPPORTED, "bf16 banks: at most 64 input channels");
+  if (pr.k != 1 && pr.k != 3 && pr.k != 5) return fail(F2D_EUNSUPPORTED, "bf16 banks: k in {1, 3, 5}");
+  BankParams p;
+  std::memset(&p, 0, sizeof(p));
+  p.src = im.data;
+  p.s_sn = im.stride_n;
+  p.s_sc = im.stride_c;
+  p.s_sh = im.stride_h;
+  p.dst = out.data;
+  p.d_sn = out.stride_n;
+  p.d_sc = out.stride_c;
+  p.d_sh = out.stride_h;
+  p.w = static_cast<const uint16_t*>(pr.filter.data);
+  p.H = im.h;
+  p.W = im.w;
+  p.row0 = pr.row_begin;
+  p.rows = pr.rows;
+  p.CI = static_cast<int32_t>(im.c);
+  p.CO = static_cast<int32_t>(pr.c_out);
+  p.fo = pr.filter.f_out;
+  p.fi = pr.filter.f_in;
+  p.o_groups = static_cast<int32_t>((pr.c_out + ot * 16 - 1) / (ot * 16));
+  p.tiles_x = static_cast<int32_t>((im.w + 63) / 64);
+  p.tiles_y = static_cast<int32_t>((pr.rows + kTH - 1) / kTH);
+  p.n_tiles = im.n * p.o_groups * static_cast<int64_t>(p.tiles_x) * p.tiles_y;
+  hipError_t e = out.dtype == F2D_BF16 ? conv_by_k<false, uint16_t, true>(p, pr.k, ot, cg, s)
+                                       : conv_by_k<false, uint16_t, false>(p, pr.k, ot, cg, s);
+  if (e == hipErrorNotSupported) return fail(F2D_EUNSUPPORTED, "bf16 banks: channel counts not supported");
+  return hip_status(e, "bf16 bank forward launch");
+}
+
+size_t bank_backward_bf16_workspace(const Problem& pr) {
+  int64_t chunks;
+  int tpu;
+  int32_t tx, ty;
+  const size_t b = wgrad_bytes(pr, &chunks, &tpu, &tx, &ty);
+  return (b + 255) & ~static_cast<size_t>(255);
+}
+
+f2d_status bank_backward_bf16(const Problem& pr, const f2d_tensor& gout, const f2d_tensor* grad_input,
+                              float* grad_filter, void* ws, size_t ws_bytes, hipStream_t s) {
+  (void)ws_bytes;
+  const f2d_tensor& im = pr.image;
+  if (pr.mode != F2D_CH_BANK) return fail(F2D_EUNSUPPORTED, "bf16 images: only BANK mode");
+  if (pr.k != 1 && pr.k != 3 && pr.k != 5) return fail(F2D_EUNSUPPORTED, "bf16 banks: k in {1, 3, 5}");
+  if (im.c > 16 || pr.c_out > 64) return fail(F2D_EUNSUPPORTED, "bf16 bank backward: C_in <= 16 and C_out <= 64");
+  const bool empty = im.n == 0 || im.c == 0 || im.h == 0 || im.w == 0 || pr.c_out == 0;
+  const bool g32 = gout.dtype == F2D_F32;
+  if (grad_input && !empty) {
+    int ot, cg;
+    if (!conv_shape(pr.c_out, im.c, &ot, &cg)) return fail(F2D_EUNSUPPORTED, "bf16 bank backward shape");
+    BankParams p;
+    std::memset(&p, 0, sizeof(p));
+    p.src = gout.data;
+    p.s_sn = gout.stride_n;
+    p.s_sc = gout.stride_c;
+    p.s_sh = gout.stride_h;
+    p.dst = grad_input->data;
+    p.d_sn = grad_input->stride_n;
+    p.d_sc = grad_input->stride_c;
+    p.d_sh = grad_input->stride_h;
+    p.w = static_cast<const uint16_t*>(pr.filter.data);
+    p.H = im.h;
+    p.W = im.w;
+    p.row0 = 0;
+    p.rows = im.h;
+    p.CI = static_cast<int32_t>(pr.c_out);
+    p.CO = static_cast<int32_t>(im.c);
+    p.fo = pr.filter.f_out;
+    p.fi = pr.filter.f_in;
+    p.o_groups = static_cast<int32_t>((im.c + ot * 16 - 1) / (ot * 16));
+    p.tiles_x = static_cast<int32_t>((im.w + 63) / 64);
+    p.tiles_y = static_cast<int32_t>((im.h + kTH - 1) / kTH);
+    p.n_tiles = im.n * p.o_groups * static_cast<int64_t>(p.tiles_x) * p.tiles_y;
+    hipError_t e = g32 ? conv_by_k<true, float, false>(p, pr.k, ot, cg, s)
+                       : conv_by_k<true, uint16_t, false>(p, pr.k, ot, cg, s);
+    if (e != hipSuccess) return hip_status(e, "bf16 bank dgrad launch");
+    EdgeParams ep;
+    std::memset(&ep, 0, sizeof(ep));
+    for (int t = 0; t < kMaxT; ++t) {
+      ep.src[t] = gout.data;
+      ep.src_sn[t] = gout.stride_n;
+      ep.src_sc[t] = gout.stride_c;
+      ep.src_sh[t] = gout.stride_h;
+    }
+    ep.out = static_cast<float*>(grad_input->data);
+    ep.out_sn = grad_input->stride_n;
+    ep.out_sc = grad_input->stride_c;
+    ep.out_sh = grad_input->stride_h;
+    ep.filt = pr.filter.data;
+    ep.H = im.h;
+    ep.W = im.w;
+    ep.planes = im.n * im.c;
+    ep.groups = static_cast<int32_t>(im.c);
+    ep.nsrc = static_cast<int32_t>(pr.c_out);
+    ep.sc_s = 1;
+    ep.fg = 1;
+    ep.fs = static_cast<int32_t>(im.c);
+    ep.k = pr.k;
+    e = launch_grad_input_edges(ep, g32 ? kEdgeF32GradBf16Filter : kEdgeBf16, s);
+    if (e != hipSuccess) return hip_status(e, "bf16 bank edge launch");
+  }
+  if (grad_filter) {
+    int64_t chunks;
+    int tpu;
+    int32_t tx, ty;
+    wgrad_bytes(pr, &chunks, &tpu, &tx, &ty);
+    const int64_t nf = pr.c_out * im.c;
+    if (!empty) {
+      WgradParams w;
+      std::memset(&w, 0, sizeof(w));
+      w.x = static_cast<const uint16_t*>(im.data);
+      w.x_sn = im.stride_n;
+      w.x_sc = im.stride_c;
+      w.x_sh = im.stride_h;
+      w.g = gout.data;
+      w.g_sn = gout.stride_n;
+      w.g_sc = gout.stride_c;
+      w.g_sh = gout.stride_h;
+      w.partial = static_cast<float*>(ws);
+      w.H = im.h;
+      w.W = im.w;
+      w.CI = static_cast<int32_t>(im.c);
+      w.CO = static_cast<int32_t>(pr.c_out);
+      w.tiles_x = tx;
+      w.tiles_y = ty;
+      w.tiles_per_unit = tpu;
+      w.chunks = static_cast<int32_t>(chunks);
+      w.o_groups = 1;
+      w.i_groups = 1;
+      w.n_units = im.n * chunks;
+      const dim3 grid(static_cast<uint32_t>(w.n_units)), block(kThreads);
+      switch (pr.k) {
+        case 1:
+          if (g32) hipLaunchKernelGGL((k_bank_wgrad<1, float>), grid, block, 0, s, w);
+          else hipLaunchKernelGGL((k_bank_wgrad<1, uint16_t>), grid, block, 0, s, w);
+          break;
+        case 3:
+          if (g32) hipLaunchKernelGGL((k_bank_wgrad<3, float>), grid, block, 0, s, w);
+          else hipLaunchKernelGGL((k_bank_wgrad<3, uint16_t>), grid, block, 0, s, w);
+          break;
+        default:
+          if (g32) hipLaunchKernelGGL((k_bank_wgrad<5, float>), grid, block, 0, s, w);
+          else hipLaunchKernelGGL((k_bank_wgrad<5, uint16_t>), grid, block, 0, s, w);
+          break;
+      }
+      hipError_t e = hipGetLastError();
+      if (e != hipSuccess) return hip_status(e, "bf16 bank wgrad launch");
+    }
+    // partial layout [unit][f][K*K] == reduce layout with nrep = units, chunks = 1
+    hipError_t e = launch_reduce_partials(static_cast<const float*>(ws), grad_filter, nf, pr.k * pr.k,
+                                          empty ? 0 : im.n * chunks, 1, s);
+    if (e != hipSuccess) return hip_status(e, "bf16 bank reduce launch");
+  }
+  return ok();
 }
 
 }  // namespace f2d

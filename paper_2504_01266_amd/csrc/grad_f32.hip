@@ -45,8 +45,29 @@ __device__ __forceinline__ void preimage(int64_t p, int64_t n, int u, int r, int
   hi = hi > n - 1 ? n - 1 : hi;
 }
 
-template <typename TG, typename TF>
+// element readers: f32, bf16 bits, or f32 rounded to bf16 (nearest even)
+struct ReadF32 {
+  using T = float;
+  __device__ static float get(const float* p) { return *p; }
+};
+struct ReadBf16 {
+  using T = uint16_t;
+  __device__ static float get(const uint16_t* p) { return __uint_as_float(static_cast<uint32_t>(*p) << 16); }
+};
+struct ReadF32AsBf16 {
+  using T = float;
+  __device__ static float get(const float* p) {
+    uint32_t u = __float_as_uint(*p);
+    if ((u & 0x7f800000u) == 0x7f800000u) return *p;
+    u += 0x7fffu + ((u >> 16) & 1u);
+    return __uint_as_float(u & 0xffff0000u);
+  }
+};
+
+template <typename RG, typename RF>
 __global__ __launch_bounds__(256) void k_grad_input_edges(EdgeParams p) {
+  using TG = typename RG::T;
+  using TF = typename RF::T;
   const int64_t idx = static_cast<int64_t>(blockIdx.x) * 256 + threadIdx.x;
   const int64_t H = p.H, W = p.W;
   const int64_t hr = H < 2 ? H : 2, wc = W < 2 ? W : 2;
@@ -84,8 +105,8 @@ __global__ __launch_bounds__(256) void k_grad_input_edges(EdgeParams p) {
         if (xlo > xhi) continue;
         float rect = 0.0f;
         for (int64_t y = ylo; y <= yhi; ++y)
-          for (int64_t x = xlo; x <= xhi; ++x) rect += static_cast<float>(gp[y * sh + x]);
-        acc = __builtin_fmaf(static_cast<float>(fp[u * K + v]), rect, acc);
+          for (int64_t x = xlo; x <= xhi; ++x) rect += RG::get(gp + y * sh + x);
+        acc = __builtin_fmaf(RF::get(fp + u * K + v), rect, acc);
       }
     }
   }
@@ -315,18 +336,20 @@ __global__ __launch_bounds__(256) void k_reduce_partials(const float* __restrict
 
 }  // namespace
 
-hipError_t launch_grad_input_edges(const EdgeParams& p, int dtype, hipStream_t s) {
+hipError_t launch_grad_input_edges(const EdgeParams& p, int kind, hipStream_t s) {
   const int64_t H = p.H, W = p.W;
   const int64_t hr = H < 2 ? H : 2, wc = W < 2 ? W : 2;
   const int64_t E = W * hr + (H > 2 ? H - 2 : 0) * wc;
   const int64_t total = E * p.planes;
   if (total <= 0) return hipSuccess;
   const int64_t blocks = (total + 255) / 256;
-  if (dtype == F2D_BF16)
-    hipLaunchKernelGGL((k_grad_input_edges<__hip_bfloat16, __hip_bfloat16>), dim3(static_cast<uint32_t>(blocks)),
-                       dim3(256), 0, s, p);
+  const dim3 grid(static_cast<uint32_t>(blocks)), block(256);
+  if (kind == kEdgeBf16)
+    hipLaunchKernelGGL((k_grad_input_edges<ReadBf16, ReadBf16>), grid, block, 0, s, p);
+  else if (kind == kEdgeF32GradBf16Filter)
+    hipLaunchKernelGGL((k_grad_input_edges<ReadF32AsBf16, ReadBf16>), grid, block, 0, s, p);
   else
-    hipLaunchKernelGGL((k_grad_input_edges<float, float>), dim3(static_cast<uint32_t>(blocks)), dim3(256), 0, s, p);
+    hipLaunchKernelGGL((k_grad_input_edges<ReadF32, ReadF32>), grid, block, 0, s, p);
   return hipGetLastError();
 }
 

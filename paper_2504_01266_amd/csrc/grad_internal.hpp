@@ -41,7 +41,11 @@ struct GradFilterParams {
   int32_t flags;  // kDstVec: G-bar rows 16-byte aligned
 };
 
-hipError_t launch_grad_input_edges(const EdgeParams& p, int dtype, hipStream_t s);
+// element types of the edge-fold kernel
+constexpr int kEdgeF32 = 0;                // f32 G-bar, f32 filter
+constexpr int kEdgeBf16 = 1;               // bf16 G-bar, bf16 filter
+constexpr int kEdgeF32GradBf16Filter = 2;  // f32 G-bar rounded to bf16, bf16 filter
+hipError_t launch_grad_input_edges(const EdgeParams& p, int kind, hipStream_t s);
 hipError_t launch_grad_filter_f32(const GradFilterParams& p, int K, hipStream_t s);
 hipError_t launch_grad_filter_generic(const GradFilterParams& p, int K, hipStream_t s);
 hipError_t launch_reduce_partials(const float* partial, float* out, int64_t nf, int kk, int64_t nrep,

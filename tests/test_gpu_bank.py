@@ -1,0 +1,150 @@
+"""BF16 filter banks on the matrix cores against the oracle.
+
+* Integer-valued BF16 operands (|v| <= 8, exact in BF16) keep every partial
+  sum an integer below 2^24, so forward, grad_input and grad_filter must equal
+  the oracle bit for bit: this pins the MFMA fragment layouts, the implicit
+  im2col indexing, the flipped/transposed adjoint weights and the clamp fold.
+* Gaussian data: relative L2 <= 1e-5 against the oracle on the BF16-rounded
+  inputs (accumulation error only), <= 1e-2 against the oracle on the
+  unrounded FP32 data (the BF16 tolerance), both reported.
+* The 32 x 16 x 1024^2 workload (C_out = 64, K = 3 and 5) in the launch
+  configuration the benchmark times: sampled rows against the oracle and the
+  adjoint identities over the whole tensors.
+"""
+import numpy as np
+import pytest
+import torch
+
+import oracle
+from paper_2504_01266_amd import workloads as wl
+
+pytestmark = pytest.mark.gpu
+
+
+def bf(a):
+    """float32 array -> (bf16 tensor on the GPU, its exact float64 values)"""
+    bits, vals = wl.bf16_round(a)
+    t = torch.from_numpy(bits.view(np.int16).copy()).view(torch.bfloat16).cuda()
+    return t, vals.astype(np.float64)
+
+
+def f32(a):
+    return torch.from_numpy(np.ascontiguousarray(a, dtype=np.float32)).cuda()
+
+
+def host(t):
+    return t.double().cpu().numpy()
+
+
+CASES = [(2, 3, 4, 37, 70), (1, 16, 64, 20, 65), (2, 16, 16, 9, 130), (1, 8, 20, 33, 64),
+         (1, 1, 1, 1, 1), (1, 16, 64, 3, 5)]
+
+
+@pytest.mark.parametrize("case", CASES)
+@pytest.mark.parametrize("k", [1, 3, 5])
+def test_integer_operands_are_bit_exact(gpu_lib, case, k):
+    n, cin, cout, h, w = case
+    r = wl.rng(30, n, cin, cout, h, w, k)
+    x = r.integers(-8, 9, (n, cin, h, w)).astype(np.float32)
+    f = r.integers(-8, 9, (cout, cin, k, k)).astype(np.float32)
+    g = r.integers(-8, 9, (n, cout, h, w)).astype(np.float32)
+    xd, xv = bf(x)
+    fd, fv = bf(f)
+    y = gpu_lib.forward(xd, fd, mode="bank")
+    assert y.dtype == torch.float32
+    assert np.array_equal(host(y), oracle.forward(xv, fv, "bank"))
+    for gdev in (bf(g)[0], f32(g)):  # bf16 or f32 upstream gradient (f32 is rounded inside)
+        gi, gf = gpu_lib.backward(xd, fd, gdev, mode="bank")
+        assert np.array_equal(host(gi), oracle.grad_input(g, fv, x.shape, "bank"))
+        assert np.array_equal(host(gf), oracle.grad_filter(xv, g, f.shape, "bank"))
+
+
+@pytest.mark.parametrize("k", [3, 5])
+def test_gaussian_data_error_vs_fp64(gpu_lib, k):
+    n, cin, cout, h, w = 2, 16, 64, 50, 97
+    r = wl.rng(31, k)
+    x = r.standard_normal((n, cin, h, w), dtype=np.float32)
+    f = (r.standard_normal((cout, cin, k, k), dtype=np.float32) *
+         np.float32(np.sqrt(2.0 / (cin * k * k))))
+    g = r.standard_normal((n, cout, h, w), dtype=np.float32)
+    xd, xv = bf(x)
+    fd, fv = bf(f)
+    gd, gv = bf(g)
+    y = host(gpu_lib.forward(xd, fd, mode="bank"))
+    assert oracle.rel_l2(y, oracle.forward(xv, fv, "bank")) <= 1e-5
+    assert oracle.rel_l2(y, oracle.forward(x, f, "bank")) <= 1e-2
+    yb = gpu_lib.forward(xd, fd, mode="bank", out_dtype=torch.bfloat16)
+    assert yb.dtype == torch.bfloat16
+    assert oracle.rel_l2(host(yb), oracle.forward(x, f, "bank")) <= 1e-2
+    gi, gf = gpu_lib.backward(xd, fd, gd, mode="bank")
+    assert oracle.rel_l2(host(gi), oracle.grad_input(gv, fv, x.shape, "bank")) <= 1e-5
+    assert oracle.rel_l2(host(gf), oracle.grad_filter(xv, gv, f.shape, "bank")) <= 1e-5
+    assert oracle.rel_l2(host(gi), oracle.grad_input(g, f, x.shape, "bank")) <= 1e-2
+    assert oracle.rel_l2(host(gf), oracle.grad_filter(x, g, f.shape, "bank")) <= 1e-2
+
+
+def test_bf16_bank_rows_band(gpu_lib):
+    k = 5
+    r = wl.rng(32)
+    x = r.standard_normal((1, 16, 60, 64), dtype=np.float32)
+    f = r.standard_normal((64, 16, k, k), dtype=np.float32) * np.float32(0.07)
+    xd, xv = bf(x)
+    fd, fv = bf(f)
+    whole = gpu_lib.forward(xd, fd, mode="bank")
+    parts = []
+    for y0, y1 in [(0, 7), (7, 31), (31, 60)]:
+        lo, hi = max(0, y0 - 2), min(60, y1 + 2)
+        parts.append(gpu_lib.forward(xd[:, :, lo:hi], fd, mode="bank", rows=(y0 - lo, y1 - lo)))
+    assert torch.equal(torch.cat(parts, dim=2), whole)
+
+
+def test_bank_backward_is_deterministic(gpu_lib):
+    r = wl.rng(33)
+    x = r.standard_normal((2, 16, 70, 130), dtype=np.float32)
+    f = r.standard_normal((64, 16, 3, 3), dtype=np.float32) * np.float32(0.1)
+    g = r.standard_normal((2, 64, 70, 130), dtype=np.float32)
+    xd, _ = bf(x)
+    fd, _ = bf(f)
+    a = gpu_lib.backward(xd, fd, f32(g), mode="bank")
+    b = gpu_lib.backward(xd, fd, f32(g), mode="bank")
+    assert torch.equal(a[0], b[0]) and torch.equal(a[1], b[1])
+
+
+@pytest.mark.parametrize("k", [3, 5])
+def test_bank_full_size(gpu_lib, k):
+    """32 x 16 x 1024^2, C_out = 64 (images and upstream gradients N(0,1), drawn
+    on the GPU with torch's seeded generator, rounded to BF16): forward rows of
+    images 0 and 31 against the oracle; grad_input and grad_filter through the
+    adjoint identities over the whole tensors (FP64 on the host side of the
+    comparison); grad_filter of a 64-row crop against the oracle."""
+    print(f"bank full size k={k}", flush=True)
+    gen = torch.Generator(device="cuda").manual_seed(5)
+    xd = torch.randn((32, 16, 1024, 1024), generator=gen, device="cuda").to(torch.bfloat16)
+    gd = torch.randn((32, 64, 1024, 1024), generator=gen, device="cuda").to(torch.bfloat16)
+    wts = wl.bank_weights(k)
+    fd, fv = bf(wts)
+    y = gpu_lib.forward(xd, fd, mode="bank")
+    torch.cuda.synchronize()
+    for nimg in (0, 31):
+        xv = host(xd[nimg:nimg + 1])
+        for (y0, y1) in [(0, 8), (508, 516), (1016, 1024)]:
+            ref = oracle.forward(xv, fv, "bank", rows=(y0, y1))
+            assert oracle.rel_l2(host(y[nimg:nimg + 1, :, y0:y1]), ref) <= 1e-5
+    gi, gf = gpu_lib.backward(xd, fd, gd, mode="bank")
+    torch.cuda.synchronize()
+    # <A x, g> = <x, A^T g> = <W, W-bar>, accumulated in FP64 one image at a time
+    lhs = rhs_x = scale = 0.0
+    for i in range(32):
+        yg = y[i].double() * gd[i].double()
+        lhs += float(yg.sum())
+        scale += float(yg.abs().sum())
+        rhs_x += float((xd[i].double() * gi[i].double()).sum())
+    rhs_w = float((fd.double() * gf.double()).sum())
+    assert abs(lhs - rhs_x) <= 1e-5 * scale
+    assert abs(lhs - rhs_w) <= 1e-5 * scale
+    # grad_filter of a crop (an independent 64-row image) against the oracle
+    xc = xd[:1, :, :64].contiguous()
+    gc = gd[:1, :, :64].contiguous()
+    _, gfc = gpu_lib.backward(xc, fd, gc, mode="bank", need_input=False)
+    ref = oracle.grad_filter(host(xc), host(gc), wts.shape, "bank")
+    assert oracle.rel_l2(host(gfc), ref) <= 1e-5
