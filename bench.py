@@ -229,7 +229,77 @@ def suite(torch, B, wl, reps):
                                "valu_frac": round(2.0 * pt / (ms * 1e-3) / 1e12 / FP32_VALU_PEAK_TFLOPS, 4)}
     del xd, yd, batch
     torch.cuda.empty_cache()
+
+    # BF16 filter bank on the matrix cores: 32 x 16 x 1024^2 -> 64 channels
+    gen = torch.Generator(device="cuda").manual_seed(5)
+    xb = torch.randn((32, 16, 1024, 1024), generator=gen, device="cuda").to(torch.bfloat16)
+    gb = torch.randn((32, 64, 1024, 1024), generator=gen, device="cuda").to(torch.bfloat16)
+    y32 = torch.empty((32, 64, 1024, 1024), device="cuda")
+    y16 = torch.empty((32, 64, 1024, 1024), dtype=torch.bfloat16, device="cuda")
+    px = 32 * 64 * 1024 * 1024
+    for k in (3, 5):
+        wk = (torch.randn((64, 16, k, k), generator=gen, device="cuda") *
+              float(np.sqrt(2.0 / (16 * k * k)))).to(torch.bfloat16)
+        flops = 2.0 * px * 16 * k * k
+        taps = px * 16 * k * k
+        for odt, yo in (("f32", y32), ("bf16", y16)):
+            ms = t.per_call_ms(lambda: B.forward(xb, wk, mode="bank", outs=[yo]), reps)
+            byts = xb.numel() * 2 + yo.numel() * yo.element_size()
+            res[f"bank_bf16_k{k}_fwd_{odt}out"] = {
+                "shape": f"32x16x1024x1024 bf16 -> 64 ch {odt}, {k}x{k}", "ms": round(ms, 4),
+                "mpix_taps_s": round(taps / (ms * 1e-3) / 1e6, 1),
+                "vs_plain_fwd": round(taps / (ms * 1e-3) / 1e6 / plain, 3),
+                "mfma": {"achieved": round(flops / (ms * 1e-3) / 1e12, 1), "peak": BF16_MFMA_PEAK_TFLOPS,
+                         "unit": "TFLOP/s", "frac": round(flops / (ms * 1e-3) / 1e12 / BF16_MFMA_PEAK_TFLOPS, 4)},
+                "hbm": {"achieved": round(byts / (ms * 1e-3) / 1e9, 1), "peak": HBM_PEAK_GBS, "unit": "GB/s",
+                        "frac": round(byts / (ms * 1e-3) / 1e9 / HBM_PEAK_GBS, 4)}}
+        ws = torch.empty(B.backward_workspace(xb, wk, mode="bank"), dtype=torch.uint8, device="cuda")
+        ms_b = t.per_call_ms(lambda: B.backward(xb, wk, gb, mode="bank", workspace=ws), reps)
+        ms_fb = t.per_call_ms(lambda: (B.forward(xb, wk, mode="bank", outs=[y32]),
+                                       B.backward(xb, wk, gb, mode="bank", workspace=ws)), reps)
+        res[f"bank_bf16_k{k}_fwd_bwd"] = {
+            "shape": f"32x16x1024x1024, 64 ch, {k}x{k}: fwd (f32 out) + grad_input + grad_filter",
+            "ms": round(ms_fb, 4), "bwd_ms": round(ms_b, 4),
+            "mpix_taps_s": round(3 * taps / (ms_fb * 1e-3) / 1e6, 1),
+            "vs_plain_fwd": round(3 * taps / (ms_fb * 1e-3) / 1e6 / plain, 3),
+            "mfma": {"achieved": round(3 * flops / (ms_fb * 1e-3) / 1e12, 1), "peak": BF16_MFMA_PEAK_TFLOPS,
+                     "unit": "TFLOP/s",
+                     "frac": round(3 * flops / (ms_fb * 1e-3) / 1e12 / BF16_MFMA_PEAK_TFLOPS, 4)}}
+        del ws
+    # the FP32 comparison path (VALU), K = 3
+    x32 = xb[:8].float()
+    w32 = (torch.randn((64, 16, 3, 3), generator=gen, device="cuda") * float(np.sqrt(2.0 / 144)))
+    y8 = torch.empty((8, 64, 1024, 1024), device="cuda")
+    ms = t.per_call_ms(lambda: B.forward(x32, w32, mode="bank", outs=[y8]), max(2, reps // 3))
+    taps = 8 * 64 * 1024 * 1024 * 16 * 9
+    res["bank_f32_k3_fwd_8img"] = {"shape": "8x16x1024x1024 f32 -> 64 ch f32, 3x3 (VALU path)",
+                                   "ms": round(ms, 4), "mpix_taps_s": round(taps / (ms * 1e-3) / 1e6, 1),
+                                   "vs_plain_fwd": round(taps / (ms * 1e-3) / 1e6 / plain, 3),
+                                   "valu_frac": round(2.0 * taps / (ms * 1e-3) / 1e12 / FP32_VALU_PEAK_TFLOPS, 4)}
+    del xb, gb, y32, y16, x32, y8
+    torch.cuda.empty_cache()
     return res
+
+
+def profile_run(torch, B, wl, steps):
+    """A short run for hardware-counter profiling: the headline kernel (tuned
+    variant) `steps` times, then one plain device copy of exactly 1 GiB (the
+    calibration kernel that converts counter readings to bytes)."""
+    x, f = wl.sobel()
+    n, c, h, w = x.shape
+    xd = torch.from_numpy(x).cuda()
+    fd = torch.from_numpy(f).cuda()
+    outs = [torch.empty((n, c, h, w), dtype=torch.int32, device="cuda") for _ in range(3)]
+    variant = B.autotune_forward(xd, fd, mode="depthwise", epilogue=B.EPI_SUMSQ_PAIRS, reps=3)
+    for _ in range(steps):
+        B.forward(xd, fd, mode="depthwise", epilogue=B.EPI_SUMSQ_PAIRS, outs=outs)
+    torch.cuda.synchronize()
+    a = torch.ones(1 << 28, dtype=torch.float32, device="cuda")  # 1 GiB
+    b = torch.empty_like(a)
+    b.copy_(a)
+    torch.cuda.synchronize()
+    print(json.dumps({"profile": "sobel-8k", "variant": variant, "steps": steps,
+                      "copy_bytes_read": a.numel() * 4, "copy_bytes_written": b.numel() * 4}), flush=True)
 
 
 def main():
@@ -241,6 +311,8 @@ def main():
     ap.add_argument("--suite-reps", type=int, default=10)
     ap.add_argument("--cpu-seconds", type=float, default=10.0, help="oracle sample budget")
     ap.add_argument("--no-cpu", action="store_true", help="skip the oracle baseline")
+    ap.add_argument("--profile", action="store_true",
+                    help="counter-profiling run: headline kernel --steps times + a 1 GiB copy")
     args = ap.parse_args()
     if args.gpus != 1:
         print(f"bench.py measures one GPU only (got --gpus {args.gpus}); the filter runs on one "
@@ -255,6 +327,9 @@ def main():
 
     B.load()
     torch.cuda.set_device(0)
+    if args.profile:
+        profile_run(torch, B, wl, args.steps)
+        return
     log("bench: headline sobel 8k")
     hd = headline(torch, B, wl, args.steps, args.warmup)
     log(f"bench: headline {hd['ms_per_step']:.4f} ms/step")

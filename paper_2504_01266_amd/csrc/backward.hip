@@ -15,6 +15,8 @@ f2d_status bank_backward_bf16(const Problem& pr, const f2d_tensor& gout, const f
                               float* grad_filter, void* ws, size_t ws_bytes, hipStream_t s);
 size_t bank_backward_bf16_workspace(const Problem& pr);
 
+size_t round_up(size_t b) { return (b + 255) & ~static_cast<size_t>(255); }
+
 namespace {
 
 struct FilterPlan {
@@ -50,18 +52,24 @@ FilterPlan filter_plan(const Problem& pr) {
   return fp;
 }
 
-size_t round_up(size_t b) { return (b + 255) & ~static_cast<size_t>(255); }
-
 bool whole_image(const Problem& pr) { return pr.row_begin == 0 && pr.row_end == pr.image.h; }
 
 }  // namespace
+
+// frame buffer of the image adjoint (templated kernels only)
+size_t frame_bytes(const Problem& pr) {
+  if (pr.k > 9) return 0;
+  const int64_t r = (pr.k - 1) / 2;
+  return round_up(static_cast<size_t>(pr.image.n * pr.image.c) *
+                  frame_plane_size(pr.image.h, pr.image.w, r) * sizeof(float));
+}
 
 size_t backward_workspace(const Problem& pr) {
   if (pr.image.dtype == F2D_BF16) return bank_backward_bf16_workspace(pr);
   if (pr.image.dtype != F2D_F32) return 0;
   const FilterPlan fp = filter_plan(pr);
   const size_t bytes = static_cast<size_t>(fp.n_units) * pr.k * pr.k * sizeof(float);
-  return round_up(bytes > 0 ? bytes : 1);
+  return frame_bytes(pr) + round_up(bytes > 0 ? bytes : 1);
 }
 
 f2d_status run_backward(const Problem& pr, const f2d_tensor* grad_outs, int32_t n_grad_outs,
@@ -94,7 +102,7 @@ f2d_status run_backward(const Problem& pr, const f2d_tensor* grad_outs, int32_t 
     if (grad_input->dtype != F2D_F32) return fail(F2D_EINVAL, "grad_input must be f32");
   }
   const size_t need = backward_workspace(pr);
-  if (grad_filter && (!ws || ws_bytes < need))
+  if ((grad_filter || grad_input) && need > 0 && (!ws || ws_bytes < need))
     return fail(F2D_EWORKSPACE, "workspace of %zu bytes needed, got %zu", need, ws ? ws_bytes : 0);
   if (im.dtype == F2D_BF16) return bank_backward_bf16(pr, grad_outs[0], grad_input, grad_filter, ws, ws_bytes, s);
 
@@ -156,21 +164,48 @@ f2d_status run_backward(const Problem& pr, const f2d_tensor* grad_outs, int32_t 
 
     const bool templ = K <= 9;
     const TileShape ts = f32_tile(templ ? 1 : -1);
-    p.tiles_x = static_cast<int32_t>((im.w + ts.tw - 1) / ts.tw);
-    p.tiles_y = static_cast<int32_t>((im.h + ts.th - 1) / ts.th);
+    const int64_t r = (K - 1) / 2;
+    if (templ) {
+      // zero-border flipped correlation over the image and its r-wide frame
+      p.row0 = -r;
+      p.rows = im.h + 2 * r;
+      p.col0 = -r;
+      p.fr = static_cast<int32_t>(r);
+      p.frame = static_cast<float*>(ws);
+      p.frame_plane = frame_plane_size(im.h, im.w, r);
+    }
+    const int64_t wext = im.w + (templ ? 2 * r : 0);
+    p.tiles_x = static_cast<int32_t>((wext + ts.tw - 1) / ts.tw);
+    p.tiles_y = static_cast<int32_t>((p.rows + ts.th - 1) / ts.th);
     p.n_blocks = im.n * p.groups * static_cast<int64_t>(p.tiles_x) * p.tiles_y;
     if (p.n_blocks > kMaxBlocks) return fail(F2D_EUNSUPPORTED, "image too large for one launch");
     if (!templ) p.flags |= kFlip | kZeroBorder;
     hipError_t err = launch_stencil_f32(p, K, 1, true, templ ? 1 : -1, s);
     if (err != hipSuccess) return hip_status(err, "grad_input launch");
-    err = launch_grad_input_edges(e, kEdgeF32, s);
+    if (templ) {
+      FoldParams fo;
+      fo.frame = p.frame;
+      fo.frame_plane = p.frame_plane;
+      fo.out = static_cast<float*>(grad_input->data);
+      fo.out_sn = grad_input->stride_n;
+      fo.out_sc = grad_input->stride_c;
+      fo.out_sh = grad_input->stride_h;
+      fo.H = im.h;
+      fo.W = im.w;
+      fo.r = r;
+      fo.planes = im.n * im.c;
+      fo.groups = im.c;
+      err = launch_fold_frame(fo, s);
+    } else {
+      err = launch_grad_input_edges(e, kEdgeF32, s);
+    }
     if (err != hipSuccess) return hip_status(err, "grad_input edge launch");
   }
 
   // --------------------------------------------------------- grad_filter --
   if (grad_filter) {
     const FilterPlan fp = filter_plan(pr);
-    float* partial = static_cast<float*>(ws);
+    float* partial = reinterpret_cast<float*>(static_cast<char*>(ws) + frame_bytes(pr));
     if (!empty) {
       GradFilterParams q;
       std::memset(&q, 0, sizeof(q));

@@ -13,10 +13,11 @@
 //                channels) in LDS and loops over 4 x (16*PT)-pixel tiles; each
 //                wave owns one tile row and OT x PT 16x16 accumulator blocks.
 //                Forward: clamp-to-edge borders.  Adjoint in the image
-//                (dgrad): zero borders and the transposed, flipped weights;
-//                the edge pixels are then recomputed exactly by the shared
-//                clamp-fold kernel.  Upstream gradients given in FP32 are
-//                rounded to BF16 (nearest even) while they are staged.
+//                (dgrad): zero borders and the transposed, flipped weights,
+//                evaluated on the image plus an r-wide frame whose values are
+//                then folded onto the edge pixels (the exact clamp adjoint).
+//                Upstream gradients given in FP32 are rounded to BF16
+//                (nearest even) while they are staged.
 //  k_bank_wgrad  W-bar[o][i][u][v] = sum_p G[o][p] * X[i][shift_uv(p)]: for
 //                every tap a 16(o) x 16(i) block contracted over 32-pixel
 //                steps; the shifted X operand is built from three aligned
@@ -39,10 +40,13 @@ namespace {
 typedef __bf16 bf16x8 __attribute__((ext_vector_type(8)));
 typedef float f32x4 __attribute__((ext_vector_type(4)));
 typedef uint32_t u32x4 __attribute__((ext_vector_type(4)));
+typedef uint16_t u16x2 __attribute__((ext_vector_type(2)));
 
-constexpr int kThreads = 256;
+constexpr int kThreads = 256;      // wgrad work-group
 constexpr int kWaves = 4;
-constexpr int kTH = 4;  // tile rows: one per wave
+constexpr int kConvThreads = 512;  // conv work-group: 8 waves, two per tile row
+constexpr int kConvWaves = 8;
+constexpr int kTH = 4;             // conv tile rows
 
 struct BankParams {
   const void* src;  // source planes: X (bf16) or, for the adjoint, G-bar (bf16 or f32)
@@ -55,6 +59,12 @@ struct BankParams {
   int32_t fo, fi;  // forward weight extents
   int32_t tiles_x, tiles_y, o_groups;
   int64_t n_tiles;  // N * o_groups * tiles_y * tiles_x
+  // adjoint: output rows start at row0 = -r and columns at col0 = -r; values
+  // on the r-wide frame go to `frame` (frame_plane floats per output plane)
+  int64_t col0;
+  float* frame;
+  int64_t frame_plane;
+  int32_t fr;
 };
 
 __device__ __forceinline__ uint16_t f32_to_bf16_bits(float f) {
@@ -87,33 +97,174 @@ struct ConvGeom {
   static constexpr int TW = 16 * PT;
   static constexpr int LH = kTH + K - 1;
   static constexpr int LW = TW + K - 1;
-  static constexpr int S_ELEMS = LH * LW * CI8 + 8;  // + one zero 16-byte slot
+  // channels-last pixel stride padded by 16 bytes: 16 lanes reading 16 bytes
+  // at consecutive pixels then cover all 64 LDS banks exactly once
+  static constexpr int PS = CI8 + 8;
+  static constexpr int S_ELEMS = LH * LW * PS + 8;  // + one zero 16-byte slot
   static constexpr int W_ELEMS = OT * 16 * WSTR;
+  static constexpr int HALO_LANES = LH * CG * (K - 1);  // staging tasks of the halo columns
+  static constexpr int TASKS = LH * CG + (HALO_LANES + 63) / 64;
+  static constexpr int NT = (TASKS + kConvWaves - 1) / kConvWaves;  // staging tasks per wave
 };
 
+// Staging of the source tile, channels-last.  Task = (row ly, channel group
+// cg) over the TW main columns (one lane per column), plus tasks that cover
+// the K-1 halo columns of every (row, group).  A lane loads the 8 channels
+// of its pixel (one load per channel plane, coalesced across the lanes of a
+// row) and later writes them as one 16-byte LDS store.  Loads always use
+// clamped, valid addresses; the border rule (clamp, or zero for the
+// adjoint) and channel padding are applied when the values are packed.
+template <int K, int CG, int LH, int TW>
+__device__ __forceinline__ void task_pos(int task, int lane, int& ly, int& cg, int& lx, bool& act) {
+  constexpr int KH = K - 1 > 0 ? K - 1 : 1;
+  if (task < LH * CG) {
+    ly = task / CG;
+    cg = task - ly * CG;
+    lx = lane;
+    act = lane < TW;
+  } else {
+    const int hl = (task - LH * CG) * 64 + lane;
+    act = hl < LH * CG * (K - 1);
+    const int h = act ? hl : 0;
+    lx = TW + h % KH;
+    const int rest = h / KH;
+    ly = rest % LH;
+    cg = rest / LH;
+  }
+}
+
+// Raw staged values of one tile for this wave: bf16 sources keep two
+// channels per register (loaded straight into the register halves), f32
+// sources one value per register (rounded to bf16 when packed).
+template <typename TS, int NT>
+struct Raw;
+template <int NT>
+struct Raw<uint16_t, NT> {
+  u16x2 v[NT][4];
+  __device__ __forceinline__ uint32_t get(int it, int c) const {
+    return (c & 1) ? v[it][c >> 1].y : v[it][c >> 1].x;
+  }
+  __device__ __forceinline__ void load(int it, int c, const uint16_t* a) {
+    if (c & 1) v[it][c >> 1].y = *a; else v[it][c >> 1].x = *a;
+  }
+};
+template <int NT>
+struct Raw<float, NT> {
+  float v[NT][8];
+  __device__ __forceinline__ uint32_t get(int it, int c) const { return f32_to_bf16_bits(v[it][c]); }
+  __device__ __forceinline__ void load(int it, int c, const float* a) { v[it][c] = *a; }
+};
+
+template <typename G, int K, int CG, typename TS>
+__device__ __forceinline__ void stage_load(const BankParams& p, int64_t n, int64_t oy0, int64_t ox0,
+                                           int wave, int lane, Raw<TS, G::NT>& st) {
+  const TS* sp = static_cast<const TS*>(p.src) + n * p.s_sn;
+#pragma unroll
+  for (int it = 0; it < G::NT; ++it) {
+    const int task = wave + kConvWaves * it;
+    if (task < G::LH * CG) {
+      // main task: uniform row and channel group, one column per lane; the
+      // channel planes are scalar bases, the column a 32-bit lane offset
+      const int ly = task / CG, cg = task - (task / CG) * CG;
+      int64_t gy = p.row0 + oy0 - G::R + ly;
+      gy = gy < 0 ? 0 : (gy >= p.H ? p.H - 1 : gy);
+      int64_t gx = ox0 - G::R + lane;
+      gx = gx < 0 ? 0 : (gx >= p.W ? p.W - 1 : gx);
+      const TS* row = sp + gy * p.s_sh;
+      const uint32_t off = static_cast<uint32_t>(gx);
+#pragma unroll
+      for (int c = 0; c < 8; ++c) {
+        const int ch = cg * 8 + c < p.CI ? cg * 8 + c : p.CI - 1;
+        st.load(it, c, row + ch * p.s_sc + off);
+      }
+    } else {
+      const int tk = task < G::TASKS ? task : 0;
+      int ly, cg, lx;
+      bool act;
+      task_pos<K, CG, G::LH, G::TW>(tk, lane, ly, cg, lx, act);
+      int64_t gy = p.row0 + oy0 - G::R + ly, gx = ox0 - G::R + lx;
+      gy = gy < 0 ? 0 : (gy >= p.H ? p.H - 1 : gy);
+      gx = gx < 0 ? 0 : (gx >= p.W ? p.W - 1 : gx);
+      const TS* px = sp + gy * p.s_sh + gx;
+#pragma unroll
+      for (int c = 0; c < 8; ++c) {
+        const int ch = cg * 8 + c < p.CI ? cg * 8 + c : p.CI - 1;
+        st.load(it, c, px + ch * p.s_sc);
+      }
+    }
+  }
+}
+
+template <typename G, int K, int CG, bool ADJ, typename TS>
+__device__ __forceinline__ void stage_store(const BankParams& p, int64_t oy0, int64_t ox0, int wave, int lane,
+                                            const Raw<TS, G::NT>& st, uint16_t* __restrict__ sl) {
+#pragma unroll
+  for (int it = 0; it < G::NT; ++it) {
+    const int task = wave + kConvWaves * it;
+    if (task >= G::TASKS) break;
+    int ly, cg, lx;
+    bool act;
+    task_pos<K, CG, G::LH, G::TW>(task, lane, ly, cg, lx, act);
+    if (!act) continue;
+    bool valid = true;
+    if constexpr (ADJ) {
+      const int64_t gy = p.row0 + oy0 - G::R + ly, gx = ox0 - G::R + lx;
+      valid = gy >= 0 && gy < p.H && gx >= 0 && gx < p.W;
+    }
+    uint32_t w[4];
+#pragma unroll
+    for (int h = 0; h < 4; ++h) {
+      const int c = cg * 8 + 2 * h;
+      const uint32_t lo = (valid && c < p.CI) ? st.get(it, 2 * h) : 0u;
+      const uint32_t hi = (valid && c + 1 < p.CI) ? st.get(it, 2 * h + 1) : 0u;
+      w[h] = lo | (hi << 16);
+    }
+    *reinterpret_cast<uint4*>(sl + (ly * G::LW + lx) * G::PS + cg * 8) = make_uint4(w[0], w[1], w[2], w[3]);
+  }
+}
+
 template <int K, int OT, int PT, int CG, bool ADJ, typename TS, bool OUT_BF16>
-__global__ __launch_bounds__(kThreads) void k_bank_conv(BankParams p) {
+__global__ __launch_bounds__(kConvThreads) void k_bank_conv(BankParams p) {
   using G = ConvGeom<K, OT, PT, CG>;
   extern __shared__ uint4 smem4[];
   uint16_t* wl = reinterpret_cast<uint16_t*>(smem4);
   uint16_t* sl = wl + G::W_ELEMS;
   const int tid = threadIdx.x;
-  const int lane = tid % 64, wave = tid / 64;
+  const int lane = tid % 64;
+  const int wave = __builtin_amdgcn_readfirstlane(tid / 64);
+  const int wrow = wave % kTH;                   // this wave's tile row
+  const int wcol = (wave / kTH) * (G::TW / 2);   // and its half of the columns
   const int l16 = lane % 16, q = lane / 16;
+  constexpr int HP = PT / 2;                     // 16-pixel blocks per wave
 
   const int64_t per_group = static_cast<int64_t>(p.tiles_x) * p.tiles_y;
-  int cur_og = -1;
-  for (int64_t t = blockIdx.x; t < p.n_tiles; t += gridDim.x) {
+  auto decode = [&](int64_t t, int64_t& n, int& og, int64_t& oy0, int64_t& ox0) {
     const int64_t ng = t / per_group;
     const int64_t r = t - ng * per_group;
-    const int og = static_cast<int>(ng % p.o_groups);
-    const int64_t n = ng / p.o_groups;
+    og = static_cast<int>(ng % p.o_groups);
+    n = ng / p.o_groups;
     const int64_t tile_y = r / p.tiles_x, tile_x = r - tile_y * p.tiles_x;
-    const int64_t oy0 = tile_y * kTH, ox0 = tile_x * G::TW;
-
+    oy0 = tile_y * kTH;
+    ox0 = (ADJ ? p.col0 : 0) + tile_x * G::TW;
+  };
+  int64_t t = blockIdx.x;
+  if (t >= p.n_tiles) return;
+  Raw<TS, G::NT> st;
+  {
+    int64_t n, oy0, ox0;
+    int og;
+    decode(t, n, og, oy0, ox0);
+    stage_load<G, K, CG, TS>(p, n, oy0, ox0, wave, lane, st);
+  }
+  int cur_og = -1;
+  while (true) {
+    int64_t n, oy0, ox0;
+    int og;
+    decode(t, n, og, oy0, ox0);
+    __syncthreads();  // the previous tile's MFMA loop is done with the LDS
     // weights of this output group, [co_local][k] with k = (uv*CG + cg)*8 + c
     if (og != cur_og) {
-      for (int idx = tid; idx < OT * 16 * G::KP; idx += kThreads) {
+      for (int idx = tid; idx < OT * 16 * G::KP; idx += kConvThreads) {
         const int col = idx / G::KP, k = idx - col * G::KP;
         const int co = og * OT * 16 + col;
         const int gi = k / 8, ci = (gi % CG) * 8 + k % 8, uv = gi / CG;
@@ -129,58 +280,49 @@ __global__ __launch_bounds__(kThreads) void k_bank_conv(BankParams p) {
       }
       cur_og = og;
     }
-    // source tile, channels-last, border rule by index arithmetic
-    const TS* sp = static_cast<const TS*>(p.src) + n * p.s_sn;
-    for (int idx = tid; idx < G::CI8 * G::LH * G::LW; idx += kThreads) {
-      const int ci = idx / (G::LH * G::LW);
-      const int rem = idx - ci * (G::LH * G::LW);
-      const int ly = rem / G::LW, lx = rem - ly * G::LW;
-      int64_t gy = p.row0 + oy0 - G::R + ly, gx = ox0 - G::R + lx;
-      uint16_t v = 0;
-      if (ci < p.CI) {
-        if constexpr (ADJ) {
-          if (gy >= 0 && gy < p.H && gx >= 0 && gx < p.W) v = load_bits<TS>(sp + ci * p.s_sc + gy * p.s_sh + gx);
-        } else {
-          gy = gy < 0 ? 0 : (gy >= p.H ? p.H - 1 : gy);
-          gx = gx < 0 ? 0 : (gx >= p.W ? p.W - 1 : gx);
-          v = load_bits<TS>(sp + ci * p.s_sc + gy * p.s_sh + gx);
-        }
-      }
-      sl[(ly * G::LW + lx) * G::CI8 + ci] = v;
-    }
+    stage_store<G, K, CG, ADJ, TS>(p, oy0, ox0, wave, lane, st, sl);
     if (tid < 8) sl[G::S_ELEMS - 8 + tid] = 0;
     __syncthreads();
+    // prefetch the next tile's source values while this tile computes
+    const int64_t t_next = t + gridDim.x;
+    if (t_next < p.n_tiles) {
+      int64_t n2, oy2, ox2;
+      int og2;
+      decode(t_next, n2, og2, oy2, ox2);
+      stage_load<G, K, CG, TS>(p, n2, oy2, ox2, wave, lane, st);
+    }
 
-    f32x4 acc[OT][PT];
+    f32x4 acc[OT][HP];
 #pragma unroll
     for (int a = 0; a < OT; ++a)
 #pragma unroll
-      for (int b = 0; b < PT; ++b) acc[a][b] = f32x4{0.f, 0.f, 0.f, 0.f};
+      for (int b = 0; b < HP; ++b) acc[a][b] = f32x4{0.f, 0.f, 0.f, 0.f};
 
     for (int s = 0; s < G::STEPS; ++s) {
       const int gi = 4 * s + q;
       const int uv = gi / CG, cg = gi - (gi / CG) * CG;
       const int u = uv / K, v = uv - (uv / K) * K;
-      bf16x8 af[OT], bfr[PT];
+      bf16x8 af[OT], bfr[HP];
 #pragma unroll
       for (int a = 0; a < OT; ++a)
         af[a] = *reinterpret_cast<const bf16x8*>(wl + (a * 16 + l16) * G::WSTR + gi * 8);
 #pragma unroll
-      for (int b = 0; b < PT; ++b) {
-        const int off = gi < G::KG ? ((wave + u) * G::LW + b * 16 + l16 + v) * G::CI8 + cg * 8
+      for (int b = 0; b < HP; ++b) {
+        const int off = gi < G::KG ? ((wrow + u) * G::LW + wcol + b * 16 + l16 + v) * G::PS + cg * 8
                                    : G::S_ELEMS - 8;
         bfr[b] = *reinterpret_cast<const bf16x8*>(sl + off);
       }
 #pragma unroll
       for (int a = 0; a < OT; ++a)
 #pragma unroll
-        for (int b = 0; b < PT; ++b)
+        for (int b = 0; b < HP; ++b)
           acc[a][b] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(af[a], bfr[b], acc[a][b], 0, 0, 0);
     }
 
     // D[o = 16a + 4q + j][pixel = 16b + l16]
-    const int64_t oy = oy0 + wave;
+    const int64_t oy = oy0 + wrow;
     if (oy < p.rows) {
+      const int64_t iy = ADJ ? p.row0 + oy : oy;  // adjoint: image row
 #pragma unroll
       for (int a = 0; a < OT; ++a)
 #pragma unroll
@@ -188,18 +330,27 @@ __global__ __launch_bounds__(kThreads) void k_bank_conv(BankParams p) {
           const int co = og * OT * 16 + a * 16 + 4 * q + j;
           if (co >= p.CO) continue;
 #pragma unroll
-          for (int b = 0; b < PT; ++b) {
-            const int64_t ox = ox0 + b * 16 + l16;
-            if (ox >= p.W) continue;
-            const int64_t o = n * p.d_sn + co * p.d_sc + oy * p.d_sh + ox;
-            if constexpr (OUT_BF16)
-              static_cast<uint16_t*>(p.dst)[o] = f32_to_bf16_bits(acc[a][b][j]);
-            else
-              static_cast<float*>(p.dst)[o] = acc[a][b][j];
+          for (int b = 0; b < HP; ++b) {
+            const int64_t ox = ox0 + wcol + b * 16 + l16;
+            if constexpr (ADJ) {
+              if (ox >= p.W + p.fr) continue;
+              if (iy >= 0 && iy < p.H && ox >= 0 && ox < p.W)
+                static_cast<float*>(p.dst)[n * p.d_sn + co * p.d_sc + iy * p.d_sh + ox] = acc[a][b][j];
+              else
+                p.frame[(n * p.CO + co) * p.frame_plane + frame_index(iy, ox, p.H, p.W, p.fr)] = acc[a][b][j];
+            } else {
+              if (ox >= p.W) continue;
+              const int64_t o = n * p.d_sn + co * p.d_sc + oy * p.d_sh + ox;
+              if constexpr (OUT_BF16)
+                static_cast<uint16_t*>(p.dst)[o] = f32_to_bf16_bits(acc[a][b][j]);
+              else
+                static_cast<float*>(p.dst)[o] = acc[a][b][j];
+            }
           }
         }
     }
-    __syncthreads();  // the next tile restages the LDS source tile
+    if (t_next >= p.n_tiles) break;
+    t = t_next;
   }
 }
 
@@ -218,15 +369,35 @@ struct WgradParams {
   int32_t CI, CO;
   int32_t tiles_x, tiles_y, tiles_per_unit, chunks;
   int32_t o_groups, i_groups;
+  int32_t x_vec, g_vec;  // rows 4-byte (x) / 16-byte-per-8-elements (g) aligned
   int64_t n_units;  // N * chunks
 };
+
+// eight consecutive elements of a 16-byte aligned row as packed bf16 pairs
+__device__ __forceinline__ void ab_vector(const uint16_t* src, uint32_t (&ab)[4]) {
+  const uint4 q = *reinterpret_cast<const uint4*>(src);
+  ab[0] = q.x;
+  ab[1] = q.y;
+  ab[2] = q.z;
+  ab[3] = q.w;
+}
+__device__ __forceinline__ void ab_vector(const float* src, uint32_t (&ab)[4]) {
+  const float4 a = reinterpret_cast<const float4*>(src)[0];
+  const float4 b = reinterpret_cast<const float4*>(src)[1];
+  const float f[8] = {a.x, a.y, a.z, a.w, b.x, b.y, b.z, b.w};
+#pragma unroll
+  for (int d = 0; d < 4; ++d)
+    ab[d] = static_cast<uint32_t>(f32_to_bf16_bits(f[2 * d])) |
+            (static_cast<uint32_t>(f32_to_bf16_bits(f[2 * d + 1])) << 16);
+}
 
 template <int K>
 struct WgGeom {
   static constexpr int R = (K - 1) / 2;
   static constexpr int LH = kWgTH + K - 1;
-  static constexpr int LWP = kWgTW + 16 + 8;  // columns x0-8 .. x0+TW+8, + 8 pad
-  static constexpr int ELEMS = 16 * LH * LWP;
+  static constexpr int LWP = kWgTW + 16;      // columns x0-8 .. x0+TW+7
+  static constexpr int PLS = LH * LWP + 8;    // channel-plane stride (elements), staggers banks
+  static constexpr int ELEMS = 16 * PLS;
 };
 
 __device__ __forceinline__ uint32_t funnel16(uint32_t hi, uint32_t lo) {
@@ -287,16 +458,29 @@ __global__ __launch_bounds__(kThreads) void k_bank_wgrad(WgradParams p) {
     const int64_t tile = chunk * p.tiles_per_unit + tt;
     if (tile >= tiles) break;
     const int64_t y0 = (tile / p.tiles_x) * kWgTH, x0 = (tile % p.tiles_x) * kWgTW;
-    // X tile [ci][row][col], clamped; LDS column c <-> source column x0 - 8 + c
-    for (int idx = tid; idx < 16 * G::LH * (kWgTW + 16); idx += kThreads) {
-      const int c = idx / (G::LH * (kWgTW + 16));
-      const int rem = idx - c * (G::LH * (kWgTW + 16));
-      const int ly = rem / (kWgTW + 16), lx = rem - ly * (kWgTW + 16);
-      int64_t gy = y0 - G::R + ly, gx = x0 - 8 + lx;
+    // X tile [ci][row][col], clamped; LDS column c <-> source column x0 - 8 + c.
+    // Task = (channel, row); each lane stages one word (two columns).
+#pragma unroll
+    for (int it = 0; it < 16 * G::LH / kWaves; ++it) {
+      const int task = wave + kWaves * it;
+      const int c = task / G::LH, ly = task - (task / G::LH) * G::LH;
+      if (lane >= G::LWP / 2) continue;
+      int64_t gy = y0 - G::R + ly;
       gy = gy < 0 ? 0 : (gy >= p.H ? p.H - 1 : gy);
-      gx = gx < 0 ? 0 : (gx >= p.W ? p.W - 1 : gx);
       const int ci = ig * 16 + c;
-      xs[(c * G::LH + ly) * G::LWP + lx] = ci < p.CI ? xp[ci * p.x_sc + gy * p.x_sh + gx] : 0;
+      const int64_t gx = x0 - 8 + 2 * lane;
+      uint32_t v = 0;
+      if (ci < p.CI) {
+        const uint16_t* row = xp + ci * p.x_sc + gy * p.x_sh;
+        if (p.x_vec && gx >= 0 && gx + 1 < p.W) {
+          v = *reinterpret_cast<const uint32_t*>(row + gx);
+        } else {
+          const int64_t a = gx < 0 ? 0 : (gx >= p.W ? p.W - 1 : gx);
+          const int64_t b2 = gx + 1 < 0 ? 0 : (gx + 1 >= p.W ? p.W - 1 : gx + 1);
+          v = static_cast<uint32_t>(row[a]) | (static_cast<uint32_t>(row[b2]) << 16);
+        }
+      }
+      *reinterpret_cast<uint32_t*>(xs + c * G::PLS + ly * G::LWP + 2 * lane) = v;
     }
     __syncthreads();
     for (int ry = 0; ry < kWgTH; ++ry) {
@@ -306,23 +490,27 @@ __global__ __launch_bounds__(kThreads) void k_bank_wgrad(WgradParams p) {
       for (int ks = 0; ks < kWgTW / 32; ++ks) {
         const int64_t xb = x0 + ks * 32 + 8 * q;  // first of this lane's 8 pixels
         // A: G-bar[o][y][xb..xb+7], zero outside the image or past C_out
-        uint32_t ab[4];
+        uint32_t ab[4] = {0u, 0u, 0u, 0u};
+        if (o < p.CO) {
+          const TG* row = gp + o * p.g_sc + y * p.g_sh;
+          if (p.g_vec && xb + 8 <= p.W) {
+            ab_vector(row + xb, ab);
+          } else {
 #pragma unroll
-        for (int d = 0; d < 4; ++d) {
-          uint32_t lo = 0, hi = 0;
-          if (o < p.CO) {
-            const TG* row = gp + o * p.g_sc + y * p.g_sh;
-            if (xb + 2 * d < p.W) lo = load_bits<TG>(row + xb + 2 * d);
-            if (xb + 2 * d + 1 < p.W) hi = load_bits<TG>(row + xb + 2 * d + 1);
+            for (int d = 0; d < 4; ++d) {
+              uint32_t lo = 0, hi = 0;
+              if (xb + 2 * d < p.W) lo = load_bits<TG>(row + xb + 2 * d);
+              if (xb + 2 * d + 1 < p.W) hi = load_bits<TG>(row + xb + 2 * d + 1);
+              ab[d] = lo | (hi << 16);
+            }
           }
-          ab[d] = lo | (hi << 16);
         }
         const bf16x8 a = __builtin_bit_cast(bf16x8, u32x4{ab[0], ab[1], ab[2], ab[3]});
 #pragma unroll
         for (int u = 0; u < K; ++u) {
           // LDS row ry+u of channel l16; columns ks*32 + 8q + {0..23}
           const uint32_t* rw = reinterpret_cast<const uint32_t*>(
-              xs + (l16 * G::LH + ry + u) * G::LWP + ks * 32 + 8 * q);
+              xs + l16 * G::PLS + (ry + u) * G::LWP + ks * 32 + 8 * q);
           uint32_t w[12];
 #pragma unroll
           for (int c = 0; c < 3; ++c) {
@@ -372,7 +560,7 @@ hipError_t conv_go(const BankParams& p, hipStream_t s) {
                               static_cast<int>(lds));
       if (e != hipSuccess) return e;
       int per_cu = 0, cus = 0;
-      e = hipOccupancyMaxActiveBlocksPerMultiprocessor(&per_cu, kern, kThreads, lds);
+      e = hipOccupancyMaxActiveBlocksPerMultiprocessor(&per_cu, kern, kConvThreads, lds);
       if (e != hipSuccess) return e;
       e = hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, dev);
       if (e != hipSuccess) return e;
@@ -383,8 +571,8 @@ hipError_t conv_go(const BankParams& p, hipStream_t s) {
   }
   const int64_t g = p.n_tiles < grid ? p.n_tiles : grid;
   if (g <= 0) return hipSuccess;
-  hipLaunchKernelGGL((k_bank_conv<K, OT, PT, CG, ADJ, TS, OB>), dim3(static_cast<uint32_t>(g)), dim3(kThreads),
-                     lds, s, p);
+  hipLaunchKernelGGL((k_bank_conv<K, OT, PT, CG, ADJ, TS, OB>), dim3(static_cast<uint32_t>(g)),
+                     dim3(kConvThreads), lds, s, p);
   return hipGetLastError();
 }
 
@@ -481,12 +669,19 @@ f2d_status bank_forward_bf16(const Problem& pr, const f2d_tensor* outs, hipStrea
   return hip_status(e, "bf16 bank forward launch");
 }
 
+size_t bank_frame_bytes(const Problem& pr) {
+  const int64_t r = (pr.k - 1) / 2;
+  const size_t b = static_cast<size_t>(pr.image.n * pr.image.c) *
+                   frame_plane_size(pr.image.h, pr.image.w, r) * sizeof(float);
+  return (b + 255) & ~static_cast<size_t>(255);
+}
+
 size_t bank_backward_bf16_workspace(const Problem& pr) {
   int64_t chunks;
   int tpu;
   int32_t tx, ty;
   const size_t b = wgrad_bytes(pr, &chunks, &tpu, &tx, &ty);
-  return (b + 255) & ~static_cast<size_t>(255);
+  return bank_frame_bytes(pr) + ((b + 255) & ~static_cast<size_t>(255)) + 256;
 }
 
 f2d_status bank_backward_bf16(const Problem& pr, const f2d_tensor& gout, const f2d_tensor* grad_input,
@@ -512,45 +707,40 @@ f2d_status bank_backward_bf16(const Problem& pr, const f2d_tensor& gout, const f
     p.d_sc = grad_input->stride_c;
     p.d_sh = grad_input->stride_h;
     p.w = static_cast<const uint16_t*>(pr.filter.data);
+    const int64_t r = (pr.k - 1) / 2;
     p.H = im.h;
     p.W = im.w;
-    p.row0 = 0;
-    p.rows = im.h;
+    p.row0 = -r;  // the image and its r-wide frame
+    p.rows = im.h + 2 * r;
+    p.col0 = -r;
+    p.fr = static_cast<int32_t>(r);
+    p.frame = static_cast<float*>(ws);
+    p.frame_plane = frame_plane_size(im.h, im.w, r);
     p.CI = static_cast<int32_t>(pr.c_out);
     p.CO = static_cast<int32_t>(im.c);
     p.fo = pr.filter.f_out;
     p.fi = pr.filter.f_in;
     p.o_groups = static_cast<int32_t>((im.c + ot * 16 - 1) / (ot * 16));
-    p.tiles_x = static_cast<int32_t>((im.w + 63) / 64);
-    p.tiles_y = static_cast<int32_t>((im.h + kTH - 1) / kTH);
+    p.tiles_x = static_cast<int32_t>((im.w + 2 * r + 63) / 64);
+    p.tiles_y = static_cast<int32_t>((p.rows + kTH - 1) / kTH);
     p.n_tiles = im.n * p.o_groups * static_cast<int64_t>(p.tiles_x) * p.tiles_y;
     hipError_t e = g32 ? conv_by_k<true, float, false>(p, pr.k, ot, cg, s)
                        : conv_by_k<true, uint16_t, false>(p, pr.k, ot, cg, s);
     if (e != hipSuccess) return hip_status(e, "bf16 bank dgrad launch");
-    EdgeParams ep;
-    std::memset(&ep, 0, sizeof(ep));
-    for (int t = 0; t < kMaxT; ++t) {
-      ep.src[t] = gout.data;
-      ep.src_sn[t] = gout.stride_n;
-      ep.src_sc[t] = gout.stride_c;
-      ep.src_sh[t] = gout.stride_h;
-    }
-    ep.out = static_cast<float*>(grad_input->data);
-    ep.out_sn = grad_input->stride_n;
-    ep.out_sc = grad_input->stride_c;
-    ep.out_sh = grad_input->stride_h;
-    ep.filt = pr.filter.data;
-    ep.H = im.h;
-    ep.W = im.w;
-    ep.planes = im.n * im.c;
-    ep.groups = static_cast<int32_t>(im.c);
-    ep.nsrc = static_cast<int32_t>(pr.c_out);
-    ep.sc_s = 1;
-    ep.fg = 1;
-    ep.fs = static_cast<int32_t>(im.c);
-    ep.k = pr.k;
-    e = launch_grad_input_edges(ep, g32 ? kEdgeF32GradBf16Filter : kEdgeBf16, s);
-    if (e != hipSuccess) return hip_status(e, "bf16 bank edge launch");
+    FoldParams fo;
+    fo.frame = p.frame;
+    fo.frame_plane = p.frame_plane;
+    fo.out = static_cast<float*>(grad_input->data);
+    fo.out_sn = grad_input->stride_n;
+    fo.out_sc = grad_input->stride_c;
+    fo.out_sh = grad_input->stride_h;
+    fo.H = im.h;
+    fo.W = im.w;
+    fo.r = r;
+    fo.planes = im.n * im.c;
+    fo.groups = im.c;
+    e = launch_fold_frame(fo, s);
+    if (e != hipSuccess) return hip_status(e, "bf16 bank fold launch");
   }
   if (grad_filter) {
     int64_t chunks;
@@ -569,7 +759,7 @@ f2d_status bank_backward_bf16(const Problem& pr, const f2d_tensor& gout, const f
       w.g_sn = gout.stride_n;
       w.g_sc = gout.stride_c;
       w.g_sh = gout.stride_h;
-      w.partial = static_cast<float*>(ws);
+      w.partial = reinterpret_cast<float*>(static_cast<char*>(ws) + bank_frame_bytes(pr));
       w.H = im.h;
       w.W = im.w;
       w.CI = static_cast<int32_t>(im.c);
@@ -580,6 +770,8 @@ f2d_status bank_backward_bf16(const Problem& pr, const f2d_tensor& gout, const f
       w.chunks = static_cast<int32_t>(chunks);
       w.o_groups = 1;
       w.i_groups = 1;
+      w.x_vec = row_aligned(im, 4) ? 1 : 0;
+      w.g_vec = row_aligned(gout, g32 ? 32 : 16) ? 1 : 0;
       w.n_units = im.n * chunks;
       const dim3 grid(static_cast<uint32_t>(w.n_units)), block(kThreads);
       switch (pr.k) {
@@ -600,7 +792,9 @@ f2d_status bank_backward_bf16(const Problem& pr, const f2d_tensor& gout, const f
       if (e != hipSuccess) return hip_status(e, "bf16 bank wgrad launch");
     }
     // partial layout [unit][f][K*K] == reduce layout with nrep = units, chunks = 1
-    hipError_t e = launch_reduce_partials(static_cast<const float*>(ws), grad_filter, nf, pr.k * pr.k,
+    hipError_t e = launch_reduce_partials(
+        reinterpret_cast<const float*>(static_cast<const char*>(ws) + bank_frame_bytes(pr)), grad_filter, nf,
+        pr.k * pr.k,
                                           empty ? 0 : im.n * chunks, 1, s);
     if (e != hipSuccess) return hip_status(e, "bf16 bank reduce launch");
   }

@@ -34,7 +34,28 @@ struct StencilParams {
   int64_t n_blocks;  // N * groups * tiles_y * tiles_x
   int32_t k;         // runtime K (generic kernel)
   int32_t flags;     // kFlip | kZeroBorder | kSumSq (generic / u8 kernels)
+  // image adjoint only: output columns start at col0 (= -r) and rows at row0
+  // (= -r), covering the image plus an r-wide frame; values that fall on the
+  // frame go to `frame` (frame_plane floats per output plane, frame_index()).
+  int64_t col0;
+  float* frame;
+  int64_t frame_plane;
+  int32_t fr;
 };
+
+// Layout of the r-wide frame around an H x W plane: the r rows above and the
+// r rows below (each W + 2r wide, corners included), then the left and the
+// right r columns of the H image rows.
+__host__ __device__ inline int64_t frame_plane_size(int64_t H, int64_t W, int64_t r) {
+  return 2 * r * (W + 2 * r) + 2 * r * H;
+}
+__host__ __device__ inline int64_t frame_index(int64_t iy, int64_t ix, int64_t H, int64_t W, int64_t r) {
+  const int64_t we = W + 2 * r;
+  if (iy < 0) return (iy + r) * we + (ix + r);
+  if (iy >= H) return (r + iy - H) * we + (ix + r);
+  if (ix < 0) return 2 * r * we + iy * r + (ix + r);
+  return 2 * r * we + H * r + iy * r + (ix - W);
+}
 
 constexpr int32_t kFlip = 1;       // use F[K-1-u][K-1-v] (image adjoint)
 constexpr int32_t kZeroBorder = 2; // out-of-range source pixels read as 0

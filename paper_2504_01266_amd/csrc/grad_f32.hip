@@ -2,14 +2,15 @@
 //
 // grad_input.  The forward map reads X at clamped indices, so its adjoint is
 // "correlate the zero-padded upstream gradient with the flipped filter, then
-// fold the gradient that fell outside the image back onto the edge pixels".
-// The flipped-filter correlation with zero borders is the VALU stencil kernel
-// (adjoint mode).  It is exact for every pixel off the outermost rows and
-// columns.  k_grad_input_edges then recomputes each edge pixel (p, q) from
-// the definition: for every tap (u, v), every output (y, x) whose clamped
-// source is (p, q) contributes, and those outputs form the rectangle
-// {y : cl(y+u-r) = p} x {x : cl(x+v-r) = q}.  Edge pixels are a vanishing
-// fraction of the image, so this is cheap.
+// fold the gradient that fell outside the image back onto the edge pixels":
+// X-bar[p][q] = sum of Z[a][b] over every (a, b) with cl(a) = p, cl(b) = q,
+// where Z is that correlation evaluated on the image and an r-wide frame
+// around it.  The VALU stencil kernel (adjoint mode) evaluates Z, writing the
+// image part to X-bar and the frame part to a frame buffer; k_fold_frame adds
+// each edge pixel's frame values.  The runtime-K path (K > 9) instead
+// recomputes each edge pixel from the definition in k_grad_input_edges: for
+// every tap (u, v) the outputs whose clamped source is (p, q) form the
+// rectangle {y : cl(y+u-r) = p} x {x : cl(x+v-r) = q}.
 //
 // grad_filter.  F-bar[u][v] sums G-bar[y][x] * X[cl(y+u-r)][cl(x+v-r)] over
 // every pixel of every plane pair that the filter touches.  A work-group
@@ -45,25 +46,11 @@ __device__ __forceinline__ void preimage(int64_t p, int64_t n, int u, int r, int
   hi = hi > n - 1 ? n - 1 : hi;
 }
 
-// element readers: f32, bf16 bits, or f32 rounded to bf16 (nearest even)
+// element reader (the edge kernel serves the f32 runtime-K path)
 struct ReadF32 {
   using T = float;
   __device__ static float get(const float* p) { return *p; }
 };
-struct ReadBf16 {
-  using T = uint16_t;
-  __device__ static float get(const uint16_t* p) { return __uint_as_float(static_cast<uint32_t>(*p) << 16); }
-};
-struct ReadF32AsBf16 {
-  using T = float;
-  __device__ static float get(const float* p) {
-    uint32_t u = __float_as_uint(*p);
-    if ((u & 0x7f800000u) == 0x7f800000u) return *p;
-    u += 0x7fffu + ((u >> 16) & 1u);
-    return __uint_as_float(u & 0xffff0000u);
-  }
-};
-
 template <typename RG, typename RF>
 __global__ __launch_bounds__(256) void k_grad_input_edges(EdgeParams p) {
   using TG = typename RG::T;
@@ -111,6 +98,39 @@ __global__ __launch_bounds__(256) void k_grad_input_edges(EdgeParams p) {
     }
   }
   p.out[n * p.out_sn + g * p.out_sc + py * p.out_sh + px] = acc;
+}
+
+// Fold the frame onto the edge pixels: X-bar[p][q] += every frame value
+// Z[a][b] with cl(a) = p and cl(b) = q, in a fixed order.
+__global__ __launch_bounds__(256) void k_fold_frame(FoldParams p) {
+  const int64_t idx = static_cast<int64_t>(blockIdx.x) * 256 + threadIdx.x;
+  const int64_t H = p.H, W = p.W, r = p.r;
+  const int64_t hr = H < 2 ? H : 2, wc = W < 2 ? W : 2;
+  const int64_t E = W * hr + (H > 2 ? H - 2 : 0) * wc;
+  if (idx >= E * p.planes) return;
+  const int64_t plane = idx / E;
+  int64_t e = idx - plane * E;
+  int64_t py, px;
+  if (e < W * hr) {
+    py = e < W ? 0 : H - 1;
+    px = e < W ? e : e - W;
+  } else {
+    e -= W * hr;
+    py = 1 + e / wc;
+    px = (e % wc) == 0 ? 0 : W - 1;
+  }
+  const int64_t alo = py == 0 ? -r : py, ahi = py == H - 1 ? H - 1 + r : py;
+  const int64_t blo = px == 0 ? -r : px, bhi = px == W - 1 ? W - 1 + r : px;
+  const float* fr = p.frame + plane * p.frame_plane;
+  float s = 0.0f;
+  for (int64_t a = alo; a <= ahi; ++a)
+    for (int64_t b = blo; b <= bhi; ++b) {
+      if (a >= 0 && a < H && b >= 0 && b < W) continue;  // the pixel itself
+      s += fr[frame_index(a, b, H, W, r)];
+    }
+  const int64_t n = plane / p.groups, g = plane - n * p.groups;
+  float* o = p.out + n * p.out_sn + g * p.out_sc + py * p.out_sh + px;
+  *o = *o + s;
 }
 
 // ----------------------------------------------------------- grad_filter --
@@ -344,12 +364,17 @@ hipError_t launch_grad_input_edges(const EdgeParams& p, int kind, hipStream_t s)
   if (total <= 0) return hipSuccess;
   const int64_t blocks = (total + 255) / 256;
   const dim3 grid(static_cast<uint32_t>(blocks)), block(256);
-  if (kind == kEdgeBf16)
-    hipLaunchKernelGGL((k_grad_input_edges<ReadBf16, ReadBf16>), grid, block, 0, s, p);
-  else if (kind == kEdgeF32GradBf16Filter)
-    hipLaunchKernelGGL((k_grad_input_edges<ReadF32AsBf16, ReadBf16>), grid, block, 0, s, p);
-  else
-    hipLaunchKernelGGL((k_grad_input_edges<ReadF32, ReadF32>), grid, block, 0, s, p);
+  if (kind != kEdgeF32) return hipErrorInvalidValue;
+  hipLaunchKernelGGL((k_grad_input_edges<ReadF32, ReadF32>), grid, block, 0, s, p);
+  return hipGetLastError();
+}
+
+hipError_t launch_fold_frame(const FoldParams& p, hipStream_t s) {
+  const int64_t H = p.H, W = p.W;
+  const int64_t hr = H < 2 ? H : 2, wc = W < 2 ? W : 2;
+  const int64_t total = (W * hr + (H > 2 ? H - 2 : 0) * wc) * p.planes;
+  if (total <= 0 || p.r == 0) return hipSuccess;
+  hipLaunchKernelGGL(k_fold_frame, dim3(static_cast<uint32_t>((total + 255) / 256)), dim3(256), 0, s, p);
   return hipGetLastError();
 }
 

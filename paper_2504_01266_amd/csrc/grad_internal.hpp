@@ -41,10 +41,19 @@ struct GradFilterParams {
   int32_t flags;  // kDstVec: G-bar rows 16-byte aligned
 };
 
-// element types of the edge-fold kernel
-constexpr int kEdgeF32 = 0;                // f32 G-bar, f32 filter
-constexpr int kEdgeBf16 = 1;               // bf16 G-bar, bf16 filter
-constexpr int kEdgeF32GradBf16Filter = 2;  // f32 G-bar rounded to bf16, bf16 filter
+// The r-wide frame of the image adjoint, folded onto the edge pixels of out.
+struct FoldParams {
+  const float* frame;
+  int64_t frame_plane;
+  float* out;
+  int64_t out_sn, out_sc, out_sh;
+  int64_t H, W, r;
+  int64_t planes, groups;
+};
+hipError_t launch_fold_frame(const FoldParams& p, hipStream_t s);
+
+// element types of the rectangle-sum edge kernel (runtime-K f32 path)
+constexpr int kEdgeF32 = 0;
 hipError_t launch_grad_input_edges(const EdgeParams& p, int kind, hipStream_t s);
 hipError_t launch_grad_filter_f32(const GradFilterParams& p, int K, hipStream_t s);
 hipError_t launch_grad_filter_generic(const GradFilterParams& p, int K, hipStream_t s);

@@ -52,6 +52,41 @@ __device__ __forceinline__ void store_outputs(const StencilParams& p, int64_t n,
   }
 }
 
+// Image adjoint store: image coordinates (iy, ix) = (row0 + oy, ox); pixels
+// inside the image go to the output plane, pixels on the r-wide frame to the
+// frame buffer (folded onto the edge pixels afterwards).
+template <int PX, int PY>
+__device__ __forceinline__ void store_adjoint(const StencilParams& p, int64_t n, int64_t g, int64_t oy0,
+                                              int64_t ox0, const float (&acc)[PY][PX]) {
+  const bool vec = (p.flags & kDstVec) != 0;
+  const int tx = threadIdx.x % kTX;
+  const int ty = threadIdx.x / kTX;
+  int64_t dsh;
+  float* dp = dst_fixed<0>(p, n, g * p.dc_g, dsh);
+  float* fp = p.frame + (n * p.groups + g) * p.frame_plane;
+  const int64_t r = p.fr;
+#pragma unroll
+  for (int jy = 0; jy < PY; ++jy) {
+    const int64_t oy = oy0 + ty * PY + jy;
+    if (oy >= p.rows) continue;
+    const int64_t iy = p.row0 + oy;
+    const int64_t ix0 = ox0 + tx * PX;
+    if (iy >= 0 && iy < p.H && ix0 >= 0 && ix0 + PX <= p.W) {
+      store_row<PX>(dp + iy * dsh, ix0, p.W, vec, acc[jy]);
+    } else {
+#pragma unroll
+      for (int px = 0; px < PX; ++px) {
+        const int64_t ix = ix0 + px;
+        if (ix >= p.W + r) continue;
+        if (iy >= 0 && iy < p.H && ix >= 0 && ix < p.W)
+          dp[iy * dsh + ix] = acc[jy][px];
+        else
+          fp[frame_index(iy, ix, p.H, p.W, r)] = acc[jy][px];
+      }
+    }
+  }
+}
+
 // MT: sources come from several tensors (the depthwise adjoint reads the m
 // upstream gradients); otherwise every source plane is in src[0].
 template <int K, int NOUT, bool ADJ, bool MT, int PX, int PY>
@@ -69,7 +104,7 @@ __global__ __launch_bounds__(kThreads) void k_stencil_f32(StencilParams p) {
   const int64_t n = plane / p.groups;
   const int64_t g = plane - n * p.groups;
   const int64_t oy0 = tile_y * G::TH;  // first output row of the tile (band-relative)
-  const int64_t ox0 = tile_x * G::TW;
+  const int64_t ox0 = (ADJ ? p.col0 : 0) + tile_x * G::TW;
 
   float acc[NOUT][PY][PX];
 #pragma unroll
@@ -104,7 +139,10 @@ __global__ __launch_bounds__(kThreads) void k_stencil_f32(StencilParams p) {
     __syncthreads();
   }
 
-  store_outputs<NOUT, PX, PY>(p, n, g, oy0, ox0, acc);
+  if constexpr (ADJ)
+    store_adjoint<PX, PY>(p, n, g, oy0, ox0, acc[0]);
+  else
+    store_outputs<NOUT, PX, PY>(p, n, g, oy0, ox0, acc);
 }
 
 // Runtime-K fallback (any odd K <= 31, NOUT = 1): one output per thread on a

@@ -362,3 +362,15 @@ def test_oracle_rejects_bad_arguments():
         oracle.forward(x, np.zeros((4, 3, 3, 3)), "bank")  # FI != C
     with pytest.raises(ValueError):
         oracle.forward(x, np.zeros((3, 3)), rows=(3, 2))
+
+
+def test_golden_constants_match_the_paper_fixtures():
+    """The constants used by the pins are the ones the paper states
+    (tests/golden: Section 4.2.4 Laplacian, Section 4.2.5 grayscale weights)."""
+    import os
+
+    here = os.path.join(os.path.dirname(__file__), "golden")
+    lap = np.loadtxt(os.path.join(here, "laplacian_3x3.txt"))
+    gray = np.loadtxt(os.path.join(here, "grayscale_weights.txt"))
+    assert np.array_equal(lap, wl.LAPLACIAN_8.astype(np.float64))
+    assert np.array_equal(gray, wl.GRAY_RGB)
