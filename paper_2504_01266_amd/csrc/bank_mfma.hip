@@ -59,12 +59,13 @@ struct BankParams {
   int32_t fo, fi;  // forward weight extents
   int32_t tiles_x, tiles_y, o_groups;
   int64_t n_tiles;  // N * o_groups * tiles_y * tiles_x
-  // adjoint: output rows start at row0 = -r and columns at col0 = -r; values
+  // adjoint: output rows start at row0 = -r and columns at col0 <= -r (4-aligned); values
   // on the r-wide frame go to `frame` (frame_plane floats per output plane)
   int64_t col0;
   float* frame;
   int64_t frame_plane;
   int32_t fr;
+  int32_t d_vec;  // output rows and planes 16-byte (f32) / 8-byte (bf16) aligned
 };
 
 __device__ __forceinline__ uint16_t f32_to_bf16_bits(float f) {
@@ -102,6 +103,9 @@ struct ConvGeom {
   static constexpr int PS = CI8 + 8;
   static constexpr int S_ELEMS = LH * LW * PS + 8;  // + one zero 16-byte slot
   static constexpr int W_ELEMS = OT * 16 * WSTR;
+  // weights + two source tiles when they fit in LDS (160 KiB), else one
+  static constexpr int NBUF = (W_ELEMS + 2 * S_ELEMS) * 2 <= 160 * 1024 ? 2 : 1;
+  static constexpr int LDS_ELEMS = W_ELEMS + NBUF * S_ELEMS;
   static constexpr int HALO_LANES = LH * CG * (K - 1);  // staging tasks of the halo columns
   static constexpr int TASKS = LH * CG + (HALO_LANES + 63) / 64;
   static constexpr int NT = (TASKS + kConvWaves - 1) / kConvWaves;  // staging tasks per wave
@@ -133,20 +137,17 @@ __device__ __forceinline__ void task_pos(int task, int lane, int& ly, int& cg, i
   }
 }
 
-// Raw staged values of one tile for this wave: bf16 sources keep two
-// channels per register (loaded straight into the register halves), f32
-// sources one value per register (rounded to bf16 when packed).
+// Raw staged values of one tile for this wave, one register per value (bf16
+// sources zero-extended, f32 sources rounded to bf16 when packed).  Packing
+// happens only in stage_store, after the MFMA loop, so the loads stay in
+// flight while the matrix cores work on the current tile.
 template <typename TS, int NT>
 struct Raw;
 template <int NT>
 struct Raw<uint16_t, NT> {
-  u16x2 v[NT][4];
-  __device__ __forceinline__ uint32_t get(int it, int c) const {
-    return (c & 1) ? v[it][c >> 1].y : v[it][c >> 1].x;
-  }
-  __device__ __forceinline__ void load(int it, int c, const uint16_t* a) {
-    if (c & 1) v[it][c >> 1].y = *a; else v[it][c >> 1].x = *a;
-  }
+  uint32_t v[NT][8];
+  __device__ __forceinline__ uint32_t get(int it, int c) const { return v[it][c]; }
+  __device__ __forceinline__ void load(int it, int c, const uint16_t* a) { v[it][c] = *a; }
 };
 template <int NT>
 struct Raw<float, NT> {
@@ -223,12 +224,90 @@ __device__ __forceinline__ void stage_store(const BankParams& p, int64_t oy0, in
   }
 }
 
+// LDS offset (elements) of tap t in the channels-last tile, relative to the
+// lane's pixel: neighbour (u, v) of the output pixel.
+template <typename G, int K>
+__device__ __forceinline__ constexpr int tap_offset(int t) {
+  return ((t / K) * G::LW + t % K) * G::PS;
+}
+
+// Step s's B-operand offset for lane quarter q, minus the lane-constant part
+// already in the base pointer.  k-group gi = 4s + q covers tap gi / CG and
+// channel group gi % CG.  With CG >= 4 the four quarters share one tap (the
+// channel group is in the base); with CG = 2 two taps alternate (one select);
+// with CG = 1 each quarter has its own tap.  s is a compile-time constant in
+// the unrolled step loop, so the taps fold to immediates.
+template <typename G, int K, int CG>
+__device__ __forceinline__ int b_step_offset(int s, bool hsel, int q) {
+  if constexpr (CG >= 4) {
+    return tap_offset<G, K>((4 * s) / CG) + ((4 * s) % CG) * 8;
+  } else if constexpr (CG == 2) {
+    const int t0 = 2 * s, t1 = 2 * s + 1;
+    return hsel ? tap_offset<G, K>(t1 < K * K ? t1 : 0) : tap_offset<G, K>(t0 < K * K ? t0 : 0);
+  } else {
+    const int t0 = 4 * s;
+    const int o0 = tap_offset<G, K>(t0 < K * K ? t0 : 0);
+    const int o1 = tap_offset<G, K>(t0 + 1 < K * K ? t0 + 1 : 0);
+    const int o2 = tap_offset<G, K>(t0 + 2 < K * K ? t0 + 2 : 0);
+    const int o3 = tap_offset<G, K>(t0 + 3 < K * K ? t0 + 3 : 0);
+    return q == 0 ? o0 : (q == 1 ? o1 : (q == 2 ? o2 : o3));
+  }
+}
+
+// Weights of output group og into LDS, [co_local][k] with k = (uv*CG + cg)*8 + c
+// (zero for padded k-groups, channels and outputs).
+template <typename G, int K, int OT, int CG, bool ADJ>
+__device__ __forceinline__ void load_weights(const BankParams& p, int og, int tid, uint16_t* __restrict__ wl) {
+  for (int idx = tid; idx < OT * 16 * G::KP; idx += kConvThreads) {
+    const int col = idx / G::KP, k = idx - col * G::KP;
+    const int co = og * OT * 16 + col;
+    const int gi = k / 8, ci = (gi % CG) * 8 + k % 8, uv = gi / CG;
+    uint16_t v = 0;
+    if (co < p.CO && gi < G::KG && ci < p.CI) {
+      const int u = uv / K, vv = uv % K;
+      if constexpr (ADJ)  // Wt[co][ci][u][v] = W[ci][co][K-1-u][K-1-v]
+        v = p.w[((static_cast<int64_t>(ci) * p.fi + co) * K + (K - 1 - u)) * K + (K - 1 - vv)];
+      else
+        v = p.w[((static_cast<int64_t>(co) * p.fi + ci) * K + u) * K + vv];
+    }
+    wl[col * G::WSTR + k] = v;
+  }
+}
+
+template <bool OUT_BF16>
+__device__ __forceinline__ void store4(void* dst, int64_t o, const f32x4& v) {
+  if constexpr (OUT_BF16) {
+    const uint32_t lo = f32_to_bf16_bits(v[0]) | (static_cast<uint32_t>(f32_to_bf16_bits(v[1])) << 16);
+    const uint32_t hi = f32_to_bf16_bits(v[2]) | (static_cast<uint32_t>(f32_to_bf16_bits(v[3])) << 16);
+    *reinterpret_cast<uint2*>(static_cast<uint16_t*>(dst) + o) = make_uint2(lo, hi);
+  } else {
+    *reinterpret_cast<float4*>(static_cast<float*>(dst) + o) = make_float4(v[0], v[1], v[2], v[3]);
+  }
+}
+template <bool OUT_BF16>
+__device__ __forceinline__ void store1(void* dst, int64_t o, float v) {
+  if constexpr (OUT_BF16)
+    static_cast<uint16_t*>(dst)[o] = f32_to_bf16_bits(v);
+  else
+    static_cast<float*>(dst)[o] = v;
+}
+
+// Persistent work-group over (image, output group, 4 x 64-pixel tile).
+// Iteration for tile t:  issue the loads of tile t+1  ->  MFMA over tile t
+// (LDS buffer c)  ->  pack tile t+1 into LDS buffer 1-c  ->  store tile t's
+// outputs  ->  one barrier.  (With a single source buffer, when two do not
+// fit in LDS, a barrier also precedes the packing.)  Stores of tile t drain while tile t+1 computes;
+// the wait for tile t+2's loads covers them only after that MFMA phase.
+//
+// MFMA operands: A = 16 pixels x 32 k (the source tile), B = 32 k x 16 output
+// channels (the weights), so D[pixel 4q + j][channel l16]: each lane holds 4
+// consecutive pixels of one output channel and writes them with one store.
 template <int K, int OT, int PT, int CG, bool ADJ, typename TS, bool OUT_BF16>
 __global__ __launch_bounds__(kConvThreads) void k_bank_conv(BankParams p) {
   using G = ConvGeom<K, OT, PT, CG>;
   extern __shared__ uint4 smem4[];
   uint16_t* wl = reinterpret_cast<uint16_t*>(smem4);
-  uint16_t* sl = wl + G::W_ELEMS;
+  uint16_t* sl0 = wl + G::W_ELEMS;
   const int tid = threadIdx.x;
   const int lane = tid % 64;
   const int wave = __builtin_amdgcn_readfirstlane(tid / 64);
@@ -236,128 +315,141 @@ __global__ __launch_bounds__(kConvThreads) void k_bank_conv(BankParams p) {
   const int wcol = (wave / kTH) * (G::TW / 2);   // and its half of the columns
   const int l16 = lane % 16, q = lane / 16;
   constexpr int HP = PT / 2;                     // 16-pixel blocks per wave
+  const uint16_t* w_lane = wl + l16 * G::WSTR + q * 8;
+  const int b_off = (wrow * G::LW + wcol + l16) * G::PS + (CG >= 4 ? q * 8 : (CG == 2 ? (q & 1) * 8 : 0));
+  const bool hsel = (q >> 1) != 0;
 
   const int64_t per_group = static_cast<int64_t>(p.tiles_x) * p.tiles_y;
-  auto decode = [&](int64_t t, int64_t& n, int& og, int64_t& oy0, int64_t& ox0) {
-    const int64_t ng = t / per_group;
-    const int64_t r = t - ng * per_group;
-    og = static_cast<int>(ng % p.o_groups);
-    n = ng / p.o_groups;
-    const int64_t tile_y = r / p.tiles_x, tile_x = r - tile_y * p.tiles_x;
-    oy0 = tile_y * kTH;
-    ox0 = (ADJ ? p.col0 : 0) + tile_x * G::TW;
+  // tile t -> (image n, output group og, tile origin); tile counts fit in 32 bits
+  const uint32_t pg = static_cast<uint32_t>(per_group), tx = static_cast<uint32_t>(p.tiles_x);
+  const uint32_t ngr = static_cast<uint32_t>(p.o_groups);
+  auto decode = [&](int64_t t64, int64_t& n, int& og, int64_t& oy0, int64_t& ox0) {
+    const uint32_t t = static_cast<uint32_t>(t64);
+    const uint32_t ng = t / pg, r = t - ng * pg;
+    og = static_cast<int>(ng % ngr);
+    n = ng / ngr;
+    const uint32_t tile_y = r / tx, tile_x = r - tile_y * tx;
+    oy0 = static_cast<int64_t>(tile_y) * kTH;
+    ox0 = (ADJ ? p.col0 : 0) + static_cast<int64_t>(tile_x) * G::TW;
   };
   int64_t t = blockIdx.x;
   if (t >= p.n_tiles) return;
+  int64_t n, oy0, ox0;
+  int og;
+  decode(t, n, og, oy0, ox0);
   Raw<TS, G::NT> st;
-  {
-    int64_t n, oy0, ox0;
-    int og;
-    decode(t, n, og, oy0, ox0);
-    stage_load<G, K, CG, TS>(p, n, oy0, ox0, wave, lane, st);
+  stage_load<G, K, CG, TS>(p, n, oy0, ox0, wave, lane, st);
+  if (tid < 8) {  // zero slot of each source buffer (never overwritten)
+    sl0[G::S_ELEMS - 8 + tid] = 0;
+    if (G::NBUF == 2) sl0[2 * G::S_ELEMS - 8 + tid] = 0;
   }
-  int cur_og = -1;
+  load_weights<G, K, OT, CG, ADJ>(p, og, tid, wl);
+  stage_store<G, K, CG, ADJ, TS>(p, oy0, ox0, wave, lane, st, sl0);
+  __syncthreads();
+  int cur = 0;
   while (true) {
-    int64_t n, oy0, ox0;
-    int og;
-    decode(t, n, og, oy0, ox0);
-    __syncthreads();  // the previous tile's MFMA loop is done with the LDS
-    // weights of this output group, [co_local][k] with k = (uv*CG + cg)*8 + c
-    if (og != cur_og) {
-      for (int idx = tid; idx < OT * 16 * G::KP; idx += kConvThreads) {
-        const int col = idx / G::KP, k = idx - col * G::KP;
-        const int co = og * OT * 16 + col;
-        const int gi = k / 8, ci = (gi % CG) * 8 + k % 8, uv = gi / CG;
-        uint16_t v = 0;
-        if (co < p.CO && gi < G::KG && ci < p.CI) {
-          const int u = uv / K, vv = uv % K;
-          if constexpr (ADJ)  // Wt[co][ci][u][v] = W[ci][co][K-1-u][K-1-v]
-            v = p.w[((static_cast<int64_t>(ci) * p.fi + co) * K + (K - 1 - u)) * K + (K - 1 - vv)];
-          else
-            v = p.w[((static_cast<int64_t>(co) * p.fi + ci) * K + u) * K + vv];
-        }
-        wl[col * G::WSTR + k] = v;
-      }
-      cur_og = og;
-    }
-    stage_store<G, K, CG, ADJ, TS>(p, oy0, ox0, wave, lane, st, sl);
-    if (tid < 8) sl[G::S_ELEMS - 8 + tid] = 0;
-    __syncthreads();
-    // prefetch the next tile's source values while this tile computes
     const int64_t t_next = t + gridDim.x;
-    if (t_next < p.n_tiles) {
-      int64_t n2, oy2, ox2;
-      int og2;
-      decode(t_next, n2, og2, oy2, ox2);
-      stage_load<G, K, CG, TS>(p, n2, oy2, ox2, wave, lane, st);
-    }
+    const bool more = t_next < p.n_tiles;
+    // prefetch the next tile (the current one again at the end: the same
+    // loads either way, so the register state has a single producer)
+    int64_t n2, oy2, ox2;
+    int og2;
+    decode(more ? t_next : t, n2, og2, oy2, ox2);
+    stage_load<G, K, CG, TS>(p, n2, oy2, ox2, wave, lane, st);
+    __builtin_amdgcn_sched_barrier(0);  // keep every prefetch load ahead of the MFMA loop
 
+    const uint16_t* sl = sl0 + cur * G::S_ELEMS;
+    const uint16_t* b_lane = sl + b_off;
     f32x4 acc[OT][HP];
 #pragma unroll
     for (int a = 0; a < OT; ++a)
 #pragma unroll
       for (int b = 0; b < HP; ++b) acc[a][b] = f32x4{0.f, 0.f, 0.f, 0.f};
-
+    // Operand addresses: a per-lane base plus a per-step constant, so that in
+    // the unrolled step loop every LDS read carries its step offset as an
+    // immediate.  Lane quarter q holds k-group gi = 4s + q of step s.
+#pragma unroll
     for (int s = 0; s < G::STEPS; ++s) {
-      const int gi = 4 * s + q;
-      const int uv = gi / CG, cg = gi - (gi / CG) * CG;
-      const int u = uv / K, v = uv - (uv / K) * K;
-      bf16x8 af[OT], bfr[HP];
+      bf16x8 wf[OT], xf[HP];
 #pragma unroll
-      for (int a = 0; a < OT; ++a)
-        af[a] = *reinterpret_cast<const bf16x8*>(wl + (a * 16 + l16) * G::WSTR + gi * 8);
+      for (int a = 0; a < OT; ++a) wf[a] = *reinterpret_cast<const bf16x8*>(w_lane + a * 16 * G::WSTR + 32 * s);
+      const uint16_t* bp = b_lane + b_step_offset<G, K, CG>(s, hsel, q);
+      if (4 * s + 3 >= G::KG && 4 * s + q >= G::KG) bp = sl + (G::S_ELEMS - 8);  // padded k-group
 #pragma unroll
-      for (int b = 0; b < HP; ++b) {
-        const int off = gi < G::KG ? ((wrow + u) * G::LW + wcol + b * 16 + l16 + v) * G::PS + cg * 8
-                                   : G::S_ELEMS - 8;
-        bfr[b] = *reinterpret_cast<const bf16x8*>(sl + off);
-      }
+      for (int b = 0; b < HP; ++b) xf[b] = *reinterpret_cast<const bf16x8*>(bp + b * 16 * G::PS);
 #pragma unroll
       for (int a = 0; a < OT; ++a)
 #pragma unroll
         for (int b = 0; b < HP; ++b)
-          acc[a][b] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(af[a], bfr[b], acc[a][b], 0, 0, 0);
+          acc[a][b] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(xf[b], wf[a], acc[a][b], 0, 0, 0);
+    }
+    __builtin_amdgcn_sched_barrier(0);
+
+    if (more) {
+      // a new output group, or a single source buffer: wait until every wave
+      // is done reading (uniform branch)
+      if (og2 != og || G::NBUF == 1) __syncthreads();
+      if (og2 != og) load_weights<G, K, OT, CG, ADJ>(p, og2, tid, wl);
+      stage_store<G, K, CG, ADJ, TS>(p, oy2, ox2, wave, lane, st, sl0 + (G::NBUF == 2 ? cur ^ 1 : 0) * G::S_ELEMS);
     }
 
-    // D[o = 16a + 4q + j][pixel = 16b + l16]
+    // acc[a][b][j] = output channel og*OT*16 + 16a + l16, pixel
+    // ox0 + wcol + 16b + 4q + j of tile row wrow
     const int64_t oy = oy0 + wrow;
     if (oy < p.rows) {
       const int64_t iy = ADJ ? p.row0 + oy : oy;  // adjoint: image row
+      const int64_t ox_l = ox0 + wcol + 4 * q;
+      const int co_l = og * OT * 16 + l16;
+      const bool inside = p.d_vec && (!ADJ || (iy >= 0 && iy < p.H && ox0 + wcol >= 0)) &&
+                          ox0 + wcol + 16 * HP <= p.W;
+      if (inside) {
+        const int64_t base = n * p.d_sn + static_cast<int64_t>(co_l) * p.d_sc + iy * p.d_sh + ox_l;
 #pragma unroll
-      for (int a = 0; a < OT; ++a)
+        for (int a = 0; a < OT; ++a) {
+          if (co_l + a * 16 >= p.CO) continue;
 #pragma unroll
-        for (int j = 0; j < 4; ++j) {
-          const int co = og * OT * 16 + a * 16 + 4 * q + j;
+          for (int b = 0; b < HP; ++b) store4<OUT_BF16>(p.dst, base + a * 16 * p.d_sc + 16 * b, acc[a][b]);
+        }
+      } else {
+#pragma unroll
+        for (int a = 0; a < OT; ++a) {
+          const int co = co_l + a * 16;
           if (co >= p.CO) continue;
 #pragma unroll
-          for (int b = 0; b < HP; ++b) {
-            const int64_t ox = ox0 + wcol + b * 16 + l16;
-            if constexpr (ADJ) {
-              if (ox >= p.W + p.fr) continue;
-              if (iy >= 0 && iy < p.H && ox >= 0 && ox < p.W)
-                static_cast<float*>(p.dst)[n * p.d_sn + co * p.d_sc + iy * p.d_sh + ox] = acc[a][b][j];
-              else
-                p.frame[(n * p.CO + co) * p.frame_plane + frame_index(iy, ox, p.H, p.W, p.fr)] = acc[a][b][j];
-            } else {
-              if (ox >= p.W) continue;
-              const int64_t o = n * p.d_sn + co * p.d_sc + oy * p.d_sh + ox;
-              if constexpr (OUT_BF16)
-                static_cast<uint16_t*>(p.dst)[o] = f32_to_bf16_bits(acc[a][b][j]);
-              else
-                static_cast<float*>(p.dst)[o] = acc[a][b][j];
+          for (int b = 0; b < HP; ++b)
+#pragma unroll
+            for (int j = 0; j < 4; ++j) {
+              const int64_t ox = ox_l + 16 * b + j;
+              if constexpr (ADJ) {
+                if (ox < -p.fr || ox >= p.W + p.fr) continue;
+                if (iy >= 0 && iy < p.H && ox >= 0 && ox < p.W)
+                  store1<false>(p.dst, n * p.d_sn + co * p.d_sc + iy * p.d_sh + ox, acc[a][b][j]);
+                else
+                  p.frame[(n * p.CO + co) * p.frame_plane + frame_index(iy, ox, p.H, p.W, p.fr)] = acc[a][b][j];
+              } else {
+                if (ox >= p.W) continue;
+                store1<OUT_BF16>(p.dst, n * p.d_sn + co * p.d_sc + iy * p.d_sh + ox, acc[a][b][j]);
+              }
             }
-          }
         }
+      }
     }
-    if (t_next >= p.n_tiles) break;
+    __syncthreads();  // tile t+1 staged; everyone done with buffer cur
+    if (!more) break;
     t = t_next;
+    n = n2;
+    og = og2;
+    oy0 = oy2;
+    ox0 = ox2;
+    if (G::NBUF == 2) cur ^= 1;
   }
 }
 
 // ------------------------------------------------------------------ wgrad --
 
-constexpr int kWgTH = 8;   // rows per wgrad tile
-constexpr int kWgTW = 64;  // columns per wgrad tile (two 32-pixel steps)
+constexpr int kWgTH = 8;      // rows per wgrad tile
+constexpr int kWgTW = 64;     // columns per wgrad tile (two 32-pixel steps)
+constexpr int kWgUnits = 512; // persistent work-groups (partial sets) at most
 
 struct WgradParams {
   const uint16_t* x;  // bf16 image
@@ -367,29 +459,11 @@ struct WgradParams {
   float* partial;  // [unit][CO][CI][K*K]
   int64_t H, W;
   int32_t CI, CO;
-  int32_t tiles_x, tiles_y, tiles_per_unit, chunks;
-  int32_t o_groups, i_groups;
-  int32_t x_vec, g_vec;  // rows 4-byte (x) / 16-byte-per-8-elements (g) aligned
-  int64_t n_units;  // N * chunks
+  int32_t tiles_x, tiles_y;
+  int32_t x_vec, g_vec;  // rows 16-byte aligned (x) / 16-byte-per-8-elements (g)
+  int64_t n_tiles;       // N * tiles_y * tiles_x
+  int32_t units;         // grid size: unit u takes tiles u, u + units, ...
 };
-
-// eight consecutive elements of a 16-byte aligned row as packed bf16 pairs
-__device__ __forceinline__ void ab_vector(const uint16_t* src, uint32_t (&ab)[4]) {
-  const uint4 q = *reinterpret_cast<const uint4*>(src);
-  ab[0] = q.x;
-  ab[1] = q.y;
-  ab[2] = q.z;
-  ab[3] = q.w;
-}
-__device__ __forceinline__ void ab_vector(const float* src, uint32_t (&ab)[4]) {
-  const float4 a = reinterpret_cast<const float4*>(src)[0];
-  const float4 b = reinterpret_cast<const float4*>(src)[1];
-  const float f[8] = {a.x, a.y, a.z, a.w, b.x, b.y, b.z, b.w};
-#pragma unroll
-  for (int d = 0; d < 4; ++d)
-    ab[d] = static_cast<uint32_t>(f32_to_bf16_bits(f[2 * d])) |
-            (static_cast<uint32_t>(f32_to_bf16_bits(f[2 * d + 1])) << 16);
-}
 
 template <int K>
 struct WgGeom {
@@ -398,14 +472,16 @@ struct WgGeom {
   static constexpr int LWP = kWgTW + 16;      // columns x0-8 .. x0+TW+7
   static constexpr int PLS = LH * LWP + 8;    // channel-plane stride (elements), staggers banks
   static constexpr int ELEMS = 16 * PLS;
+  static constexpr int CHUNKS = LWP / 8;      // 16-byte chunks per staged row
+  static constexpr int STAGE = 16 * LH * CHUNKS;  // staging tasks per tile
 };
 
 __device__ __forceinline__ uint32_t funnel16(uint32_t hi, uint32_t lo) {
   return __builtin_amdgcn_alignbit(hi, lo, 16);
 }
 
-// 8 consecutive bf16 starting at element E (0 <= E <= 16) of the 24-element
-// window held in w[0..11] (two bf16 per dword, little endian).
+// 8 consecutive bf16 starting at element E (8-R <= E <= 8+R) of the window
+// held in w[0..11] (elements 0..23, two bf16 per dword, little endian).
 template <int E>
 __device__ __forceinline__ bf16x8 window8(const uint32_t (&w)[12]) {
   u32x4 r;
@@ -419,124 +495,187 @@ __device__ __forceinline__ bf16x8 window8(const uint32_t (&w)[12]) {
   return __builtin_bit_cast(bf16x8, r);
 }
 
-template <int K, int V>
-__device__ __forceinline__ void wg_taps(f32x4 (&acc)[K * K], int u, const bf16x8& a,
-                                        const uint32_t (&w)[12]) {
-  if constexpr (V < K) {
-    constexpr int R = (K - 1) / 2;
-    acc[u * K + V] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(a, window8<8 + V - R>(w), acc[u * K + V], 0, 0, 0);
-    wg_taps<K, V + 1>(acc, u, a, w);
+// eight upstream-gradient values of one row as a bf16 A fragment
+__device__ __forceinline__ bf16x8 g_fragment(const uint16_t* src) {
+  return __builtin_bit_cast(bf16x8, *reinterpret_cast<const u32x4*>(src));
+}
+__device__ __forceinline__ bf16x8 g_fragment(const float* src) {
+  const float4 a = reinterpret_cast<const float4*>(src)[0];
+  const float4 b = reinterpret_cast<const float4*>(src)[1];
+  const float f[8] = {a.x, a.y, a.z, a.w, b.x, b.y, b.z, b.w};
+  u32x4 r;
+#pragma unroll
+  for (int d = 0; d < 4; ++d)
+    r[d] = static_cast<uint32_t>(f32_to_bf16_bits(f[2 * d])) |
+           (static_cast<uint32_t>(f32_to_bf16_bits(f[2 * d + 1])) << 16);
+  return __builtin_bit_cast(bf16x8, r);
+}
+
+// A fragments of this lane for one 32-pixel step: G-bar[o][y0 + m][xb .. xb+7]
+// for the tile's rows m, zero outside the image or past C_out.
+template <typename TG>
+__device__ __forceinline__ void load_g(const WgradParams& p, const TG* gp, int o, int64_t y0, int64_t xb,
+                                       bool fast, bf16x8 (&ga)[kWgTH]) {
+#pragma unroll
+  for (int m = 0; m < kWgTH; ++m) {
+    const int64_t y = y0 + m;
+    if (fast) {
+      // interior tile: every row y < H is loaded (rows past H are zeroed)
+      const int64_t yc = y < p.H ? y : p.H - 1;
+      const bf16x8 v = g_fragment(gp + o * p.g_sc + yc * p.g_sh + xb);
+      ga[m] = y < p.H ? v : bf16x8{};
+    } else {
+      u32x4 r = u32x4{0u, 0u, 0u, 0u};
+      if (o < p.CO && y < p.H) {
+        const TG* row = gp + o * p.g_sc + y * p.g_sh;
+#pragma unroll
+        for (int d = 0; d < 4; ++d) {
+          uint32_t lo = 0, hi = 0;
+          if (xb + 2 * d < p.W) lo = load_bits<TG>(row + xb + 2 * d);
+          if (xb + 2 * d + 1 < p.W) hi = load_bits<TG>(row + xb + 2 * d + 1);
+          r[d] = lo | (hi << 16);
+        }
+      }
+      ga[m] = __builtin_bit_cast(bf16x8, r);
+    }
   }
 }
 
+// All taps of X row j of the tile against the resident G-bar rows: row j is
+// source row y0 - R + j, which meets G-bar row m = j - u at vertical tap u.
+// The K horizontal taps are shifts of one window read from LDS.
+template <int K, int J>
+__device__ __forceinline__ void wg_row(f32x4 (&acc)[K * K], const bf16x8 (&ga)[kWgTH],
+                                       const uint16_t* __restrict__ win) {
+  constexpr int R = (K - 1) / 2;
+  uint32_t w[12] = {};  // only w[2..9] are read for R <= 4
+  const uint32_t* wp = reinterpret_cast<const uint32_t*>(win + J * WgGeom<K>::LWP);
+  if constexpr (R > 0) {  // elements 4..7 and 16..19 (R <= 4)
+    const uint2 lo = *reinterpret_cast<const uint2*>(wp + 2);
+    const uint2 hi = *reinterpret_cast<const uint2*>(wp + 8);
+    w[2] = lo.x;
+    w[3] = lo.y;
+    w[8] = hi.x;
+    w[9] = hi.y;
+  }
+  const u32x4 mid = *reinterpret_cast<const u32x4*>(wp + 4);
+  w[4] = mid.x;
+  w[5] = mid.y;
+  w[6] = mid.z;
+  w[7] = mid.w;
+#pragma unroll
+  for (int u = 0; u < K; ++u) {
+    const int m = J - u;
+    if (m < 0 || m >= kWgTH) continue;
+#pragma unroll
+    for (int v = 0; v < K; ++v) {
+      bf16x8 b;
+      switch (8 + v - R) {  // compile-time after unrolling
+        case 4: b = window8<4>(w); break;
+        case 5: b = window8<5>(w); break;
+        case 6: b = window8<6>(w); break;
+        case 7: b = window8<7>(w); break;
+        case 9: b = window8<9>(w); break;
+        case 10: b = window8<10>(w); break;
+        case 11: b = window8<11>(w); break;
+        case 12: b = window8<12>(w); break;
+        default: b = window8<8>(w); break;
+      }
+      acc[u * K + v] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(ga[m], b, acc[u * K + v], 0, 0, 0);
+    }
+  }
+}
+
+template <int K, int J>
+__device__ __forceinline__ void wg_rows(f32x4 (&acc)[K * K], const bf16x8 (&ga)[kWgTH],
+                                        const uint16_t* __restrict__ win) {
+  if constexpr (J < WgGeom<K>::LH) {
+    wg_row<K, J>(acc, ga, win);
+    wg_rows<K, J + 1>(acc, ga, win);
+  }
+}
+
+// Persistent work-group over 8 x 64-pixel tiles of all images.  Wave w owns
+// output channels 16w .. 16w+15 against all (<= 16) input channels and all
+// K*K taps (acc).  Per tile: stage the clamped X tile in LDS (channel planes,
+// 16-byte chunks), then for each 32-pixel step hold the 8 G-bar row
+// fragments in registers and sweep the LH source rows once.
 template <int K, typename TG>
-__global__ __launch_bounds__(kThreads) void k_bank_wgrad(WgradParams p) {
+__global__ __launch_bounds__(kThreads) __attribute__((amdgpu_waves_per_eu(2))) void k_bank_wgrad(WgradParams p) {
   using G = WgGeom<K>;
+  static_assert(G::R <= 4, "K <= 9");
   __shared__ uint4 xs4[(G::ELEMS + 7) / 8];
   uint16_t* xs = reinterpret_cast<uint16_t*>(xs4);
-  const int tid = threadIdx.x, lane = tid % 64, wave = tid / 64;
+  const int tid = threadIdx.x, lane = tid % 64;
+  const int wave = __builtin_amdgcn_readfirstlane(tid / 64);
   const int l16 = lane % 16, q = lane / 16;
-
-  int64_t b = blockIdx.x;
-  const int ig = static_cast<int>(b % p.i_groups);
-  b /= p.i_groups;
-  const int ogp = static_cast<int>(b % p.o_groups);
-  const int64_t unit = b / p.o_groups;
-  const int64_t n = unit / p.chunks;
-  const int64_t chunk = unit - n * p.chunks;
-  const int o = ogp * 64 + wave * 16 + l16;   // A row of this lane
-  const int ci_b = ig * 16 + l16;             // B column of this lane
-  const uint16_t* xp = p.x + n * p.x_sn;
-  const TG* gp = static_cast<const TG*>(p.g) + n * p.g_sn;
+  const int o = wave * 16 + l16;  // A row (output channel) of this lane
 
   f32x4 acc[K * K];
 #pragma unroll
   for (int e = 0; e < K * K; ++e) acc[e] = f32x4{0.f, 0.f, 0.f, 0.f};
 
-  const int64_t tiles = static_cast<int64_t>(p.tiles_x) * p.tiles_y;
-  for (int tt = 0; tt < p.tiles_per_unit; ++tt) {
-    const int64_t tile = chunk * p.tiles_per_unit + tt;
-    if (tile >= tiles) break;
-    const int64_t y0 = (tile / p.tiles_x) * kWgTH, x0 = (tile % p.tiles_x) * kWgTW;
-    // X tile [ci][row][col], clamped; LDS column c <-> source column x0 - 8 + c.
-    // Task = (channel, row); each lane stages one word (two columns).
+  const int64_t per_image = static_cast<int64_t>(p.tiles_x) * p.tiles_y;
+  for (int64_t t = blockIdx.x; t < p.n_tiles; t += p.units) {
+    const int64_t n = t / per_image, r = t - n * per_image;
+    const int64_t y0 = (r / p.tiles_x) * kWgTH, x0 = (r % p.tiles_x) * kWgTW;
+    const uint16_t* xp = p.x + n * p.x_sn;
+    const TG* gp = static_cast<const TG*>(p.g) + n * p.g_sn;
+    // X tile [ci][row][col], clamped; LDS column c <-> source column x0 - 8 + c
+    const bool x_fast = p.x_vec && x0 - 8 >= 0 && x0 + kWgTW + 8 <= p.W;
+    u32x4 sv[(G::STAGE + kThreads - 1) / kThreads];
 #pragma unroll
-    for (int it = 0; it < 16 * G::LH / kWaves; ++it) {
-      const int task = wave + kWaves * it;
-      const int c = task / G::LH, ly = task - (task / G::LH) * G::LH;
-      if (lane >= G::LWP / 2) continue;
+    for (int it = 0; it < (G::STAGE + kThreads - 1) / kThreads; ++it) {
+      const int task = tid + kThreads * it < G::STAGE ? tid + kThreads * it : G::STAGE - 1;
+      const int c = task / (G::LH * G::CHUNKS), rest = task - c * (G::LH * G::CHUNKS);
+      const int ly = rest / G::CHUNKS, ch = rest - ly * G::CHUNKS;
       int64_t gy = y0 - G::R + ly;
       gy = gy < 0 ? 0 : (gy >= p.H ? p.H - 1 : gy);
-      const int ci = ig * 16 + c;
-      const int64_t gx = x0 - 8 + 2 * lane;
-      uint32_t v = 0;
-      if (ci < p.CI) {
-        const uint16_t* row = xp + ci * p.x_sc + gy * p.x_sh;
-        if (p.x_vec && gx >= 0 && gx + 1 < p.W) {
-          v = *reinterpret_cast<const uint32_t*>(row + gx);
-        } else {
-          const int64_t a = gx < 0 ? 0 : (gx >= p.W ? p.W - 1 : gx);
-          const int64_t b2 = gx + 1 < 0 ? 0 : (gx + 1 >= p.W ? p.W - 1 : gx + 1);
-          v = static_cast<uint32_t>(row[a]) | (static_cast<uint32_t>(row[b2]) << 16);
+      const int ci = c < p.CI ? c : p.CI - 1;
+      const uint16_t* row = xp + ci * p.x_sc + gy * p.x_sh;
+      const int64_t gx = x0 - 8 + 8 * ch;
+      if (x_fast) {
+        sv[it] = *reinterpret_cast<const u32x4*>(row + gx);
+      } else {
+        uint32_t h[8];
+#pragma unroll
+        for (int e = 0; e < 8; ++e) {
+          int64_t cx = gx + e;
+          cx = cx < 0 ? 0 : (cx >= p.W ? p.W - 1 : cx);
+          h[e] = row[cx];
         }
-      }
-      *reinterpret_cast<uint32_t*>(xs + c * G::PLS + ly * G::LWP + 2 * lane) = v;
-    }
-    __syncthreads();
-    for (int ry = 0; ry < kWgTH; ++ry) {
-      const int64_t y = y0 + ry;
-      if (y >= p.H) break;
-#pragma unroll
-      for (int ks = 0; ks < kWgTW / 32; ++ks) {
-        const int64_t xb = x0 + ks * 32 + 8 * q;  // first of this lane's 8 pixels
-        // A: G-bar[o][y][xb..xb+7], zero outside the image or past C_out
-        uint32_t ab[4] = {0u, 0u, 0u, 0u};
-        if (o < p.CO) {
-          const TG* row = gp + o * p.g_sc + y * p.g_sh;
-          if (p.g_vec && xb + 8 <= p.W) {
-            ab_vector(row + xb, ab);
-          } else {
-#pragma unroll
-            for (int d = 0; d < 4; ++d) {
-              uint32_t lo = 0, hi = 0;
-              if (xb + 2 * d < p.W) lo = load_bits<TG>(row + xb + 2 * d);
-              if (xb + 2 * d + 1 < p.W) hi = load_bits<TG>(row + xb + 2 * d + 1);
-              ab[d] = lo | (hi << 16);
-            }
-          }
-        }
-        const bf16x8 a = __builtin_bit_cast(bf16x8, u32x4{ab[0], ab[1], ab[2], ab[3]});
-#pragma unroll
-        for (int u = 0; u < K; ++u) {
-          // LDS row ry+u of channel l16; columns ks*32 + 8q + {0..23}
-          const uint32_t* rw = reinterpret_cast<const uint32_t*>(
-              xs + l16 * G::PLS + (ry + u) * G::LWP + ks * 32 + 8 * q);
-          uint32_t w[12];
-#pragma unroll
-          for (int c = 0; c < 3; ++c) {
-            const u32x4 t4 = *reinterpret_cast<const u32x4*>(rw + 4 * c);
-            w[4 * c + 0] = t4.x;
-            w[4 * c + 1] = t4.y;
-            w[4 * c + 2] = t4.z;
-            w[4 * c + 3] = t4.w;
-          }
-          wg_taps<K, 0>(acc, u, a, w);
-        }
+        sv[it] = u32x4{h[0] | (h[1] << 16), h[2] | (h[3] << 16), h[4] | (h[5] << 16), h[6] | (h[7] << 16)};
       }
     }
+    const bool g_fast = p.g_vec && o < p.CO && x0 + kWgTW <= p.W;
+    bf16x8 ga[kWgTH];
+    load_g<TG>(p, gp, o, y0, x0 + 8 * q, g_fast, ga);
+    __syncthreads();  // the previous tile's readers are done with the LDS
+#pragma unroll
+    for (int it = 0; it < (G::STAGE + kThreads - 1) / kThreads; ++it) {
+      const int task = tid + kThreads * it;
+      if (task >= G::STAGE) break;
+      const int c = task / (G::LH * G::CHUNKS), rest = task - c * (G::LH * G::CHUNKS);
+      const int ly = rest / G::CHUNKS, ch = rest - ly * G::CHUNKS;
+      const u32x4 v = c < p.CI ? sv[it] : u32x4{0u, 0u, 0u, 0u};
+      *reinterpret_cast<u32x4*>(xs + c * G::PLS + ly * G::LWP + 8 * ch) = v;
+    }
     __syncthreads();
+    // lane window: channel l16, columns 32 ks + 8q + {0..23} of every LDS row
+    wg_rows<K, 0>(acc, ga, xs + l16 * G::PLS + 8 * q);
+    load_g<TG>(p, gp, o, y0, x0 + 32 + 8 * q, g_fast, ga);
+    wg_rows<K, 0>(acc, ga, xs + l16 * G::PLS + 32 + 8 * q);
   }
-  // D[o = ogp*64 + wave*16 + 4q + j][ci = ig*16 + l16]
-  const int ci = ig * 16 + l16;
+  // D[o = wave*16 + 4q + j][ci = l16]
+  const int ci = l16;
 #pragma unroll
   for (int j = 0; j < 4; ++j) {
-    const int oo = ogp * 64 + wave * 16 + 4 * q + j;
+    const int oo = wave * 16 + 4 * q + j;
     if (oo >= p.CO || ci >= p.CI) continue;
-    float* dst = p.partial + ((unit * p.CO + oo) * p.CI + ci) * (K * K);
+    float* dst = p.partial + ((static_cast<int64_t>(blockIdx.x) * p.CO + oo) * p.CI + ci) * (K * K);
 #pragma unroll
     for (int e = 0; e < K * K; ++e) dst[e] = acc[e][j];
   }
-  (void)ci_b;
 }
 
 // ------------------------------------------------------------- dispatch --
@@ -544,7 +683,7 @@ __global__ __launch_bounds__(kThreads) void k_bank_wgrad(WgradParams p) {
 template <int K, int OT, int PT, int CG, bool ADJ, typename TS, bool OB>
 hipError_t conv_go(const BankParams& p, hipStream_t s) {
   using G = ConvGeom<K, OT, PT, CG>;
-  const size_t lds = static_cast<size_t>(G::W_ELEMS + G::S_ELEMS) * 2;
+  const size_t lds = static_cast<size_t>(G::LDS_ELEMS) * 2;
   if (lds > 160 * 1024) return hipErrorInvalidValue;
   static std::mutex mu;
   static int dev_cached = -1, grid_cached = 0;
@@ -586,9 +725,12 @@ hipError_t conv_by_shape(const BankParams& p, int ot, int cg, hipStream_t s) {
     if (ot == 4 && cg == 4) return conv_go<K, 4, 4, 4, ADJ, TS, OB>(p, s);
     if (ot == 2 && cg == 1) return conv_go<K, 2, 4, 1, ADJ, TS, OB>(p, s);
     if (ot == 2 && cg == 2) return conv_go<K, 2, 4, 2, ADJ, TS, OB>(p, s);
-    if (ot == 2 && cg == 8) return conv_go<K, 2, 4, 8, ADJ, TS, OB>(p, s);
+    if constexpr (K < 5) {
+      if (ot == 2 && cg == 8) return conv_go<K, 2, 4, 8, ADJ, TS, OB>(p, s);
+    }
     if (ot == 1 && cg == 1) return conv_go<K, 1, 4, 1, ADJ, TS, OB>(p, s);
     if (ot == 1 && cg == 2) return conv_go<K, 1, 4, 2, ADJ, TS, OB>(p, s);
+    if (ot == 1 && cg == 8) return conv_go<K, 1, 4, 8, ADJ, TS, OB>(p, s);
   } else {
     if (ot == 1 && cg == 8) return conv_go<K, 1, 4, 8, ADJ, TS, OB>(p, s);
     if (ot == 1 && cg == 4) return conv_go<K, 1, 4, 4, ADJ, TS, OB>(p, s);
@@ -610,25 +752,25 @@ hipError_t conv_by_k(const BankParams& p, int K, int ot, int cg, hipStream_t s) 
 
 // output-channel tiles per work-group and channel groups of 8 for a map
 // with ci source and co output channels
-bool conv_shape(int64_t ci, int64_t co, int* ot, int* cg) {
+bool conv_shape(int64_t ci, int64_t co, int k, int* ot, int* cg) {
   const int64_t g8 = (ci + 7) / 8;
   if (g8 > 8) return false;
   *cg = g8 <= 1 ? 1 : (g8 <= 2 ? 2 : (g8 <= 4 ? 4 : 8));
   *ot = co <= 16 ? 1 : (co <= 32 ? 2 : 4);
-  if (*cg == 8 && *ot == 4) *ot = 2;  // keep the weights within LDS
+  // keep weights + source tile within LDS
+  if (*cg == 8 && *ot == 4) *ot = 2;
+  if (*cg == 8 && k == 5) *ot = 1;
   return true;
 }
 
-size_t wgrad_bytes(const Problem& pr, int64_t* chunks, int* tpu, int32_t* tx, int32_t* ty) {
+// persistent wgrad grid: units work-groups over n_tiles tiles
+size_t wgrad_bytes(const Problem& pr, int32_t* units, int64_t* n_tiles, int32_t* tx, int32_t* ty) {
   const f2d_tensor& im = pr.image;
   *tx = static_cast<int32_t>((im.w + kWgTW - 1) / kWgTW);
   *ty = static_cast<int32_t>((im.h + kWgTH - 1) / kWgTH);
-  const int64_t tiles = static_cast<int64_t>(*tx) * *ty;
-  int64_t t = tiles * im.n / 2048;  // aim at >= ~2048 work-groups
-  t = t < 1 ? 1 : (t > 32 ? 32 : t);
-  *tpu = static_cast<int>(t);
-  *chunks = (tiles + t - 1) / t;
-  return static_cast<size_t>(im.n * *chunks) * pr.c_out * im.c * pr.k * pr.k * sizeof(float);
+  *n_tiles = im.n * static_cast<int64_t>(*tx) * *ty;
+  *units = static_cast<int32_t>(*n_tiles < kWgUnits ? *n_tiles : kWgUnits);
+  return static_cast<size_t>(*units) * pr.c_out * im.c * pr.k * pr.k * sizeof(float);
 }
 
 }  // namespace
@@ -637,7 +779,7 @@ f2d_status bank_forward_bf16(const Problem& pr, const f2d_tensor* outs, hipStrea
   const f2d_tensor& im = pr.image;
   const f2d_tensor& out = outs[0];
   int ot, cg;
-  if (!conv_shape(im.c, pr.c_out, &ot, &cg))
+  if (!conv_shape(im.c, pr.c_out, pr.k, &ot, &cg))
     return fail(F2D_EUNSUPPORTED, "bf16 banks: at most 64 input channels");
   if (pr.k != 1 && pr.k != 3 && pr.k != 5) return fail(F2D_EUNSUPPORTED, "bf16 banks: k in {1, 3, 5}");
   BankParams p;
@@ -650,6 +792,7 @@ f2d_status bank_forward_bf16(const Problem& pr, const f2d_tensor* outs, hipStrea
   p.d_sn = out.stride_n;
   p.d_sc = out.stride_c;
   p.d_sh = out.stride_h;
+  p.d_vec = row_aligned(out, out.dtype == F2D_BF16 ? 8 : 16) ? 1 : 0;
   p.w = static_cast<const uint16_t*>(pr.filter.data);
   p.H = im.h;
   p.W = im.w;
@@ -677,10 +820,9 @@ size_t bank_frame_bytes(const Problem& pr) {
 }
 
 size_t bank_backward_bf16_workspace(const Problem& pr) {
-  int64_t chunks;
-  int tpu;
-  int32_t tx, ty;
-  const size_t b = wgrad_bytes(pr, &chunks, &tpu, &tx, &ty);
+  int32_t units, tx, ty;
+  int64_t n_tiles;
+  const size_t b = wgrad_bytes(pr, &units, &n_tiles, &tx, &ty);
   return bank_frame_bytes(pr) + ((b + 255) & ~static_cast<size_t>(255)) + 256;
 }
 
@@ -695,7 +837,7 @@ f2d_status bank_backward_bf16(const Problem& pr, const f2d_tensor& gout, const f
   const bool g32 = gout.dtype == F2D_F32;
   if (grad_input && !empty) {
     int ot, cg;
-    if (!conv_shape(pr.c_out, im.c, &ot, &cg)) return fail(F2D_EUNSUPPORTED, "bf16 bank backward shape");
+    if (!conv_shape(pr.c_out, im.c, pr.k, &ot, &cg)) return fail(F2D_EUNSUPPORTED, "bf16 bank backward shape");
     BankParams p;
     std::memset(&p, 0, sizeof(p));
     p.src = gout.data;
@@ -706,13 +848,15 @@ f2d_status bank_backward_bf16(const Problem& pr, const f2d_tensor& gout, const f
     p.d_sn = grad_input->stride_n;
     p.d_sc = grad_input->stride_c;
     p.d_sh = grad_input->stride_h;
+    p.d_vec = row_aligned(*grad_input, 16) ? 1 : 0;
     p.w = static_cast<const uint16_t*>(pr.filter.data);
     const int64_t r = (pr.k - 1) / 2;
     p.H = im.h;
     p.W = im.w;
     p.row0 = -r;  // the image and its r-wide frame
     p.rows = im.h + 2 * r;
-    p.col0 = -r;
+    // tile columns start 4-aligned left of the frame (columns < -r are skipped)
+    p.col0 = -((r + 3) / 4) * 4;
     p.fr = static_cast<int32_t>(r);
     p.frame = static_cast<float*>(ws);
     p.frame_plane = frame_plane_size(im.h, im.w, r);
@@ -721,7 +865,7 @@ f2d_status bank_backward_bf16(const Problem& pr, const f2d_tensor& gout, const f
     p.fo = pr.filter.f_out;
     p.fi = pr.filter.f_in;
     p.o_groups = static_cast<int32_t>((im.c + ot * 16 - 1) / (ot * 16));
-    p.tiles_x = static_cast<int32_t>((im.w + 2 * r + 63) / 64);
+    p.tiles_x = static_cast<int32_t>((im.w + r - p.col0 + 63) / 64);
     p.tiles_y = static_cast<int32_t>((p.rows + kTH - 1) / kTH);
     p.n_tiles = im.n * p.o_groups * static_cast<int64_t>(p.tiles_x) * p.tiles_y;
     hipError_t e = g32 ? conv_by_k<true, float, false>(p, pr.k, ot, cg, s)
@@ -743,10 +887,9 @@ f2d_status bank_backward_bf16(const Problem& pr, const f2d_tensor& gout, const f
     if (e != hipSuccess) return hip_status(e, "bf16 bank fold launch");
   }
   if (grad_filter) {
-    int64_t chunks;
-    int tpu;
-    int32_t tx, ty;
-    wgrad_bytes(pr, &chunks, &tpu, &tx, &ty);
+    int32_t units, tx, ty;
+    int64_t n_tiles;
+    wgrad_bytes(pr, &units, &n_tiles, &tx, &ty);
     const int64_t nf = pr.c_out * im.c;
     if (!empty) {
       WgradParams w;
@@ -766,14 +909,11 @@ f2d_status bank_backward_bf16(const Problem& pr, const f2d_tensor& gout, const f
       w.CO = static_cast<int32_t>(pr.c_out);
       w.tiles_x = tx;
       w.tiles_y = ty;
-      w.tiles_per_unit = tpu;
-      w.chunks = static_cast<int32_t>(chunks);
-      w.o_groups = 1;
-      w.i_groups = 1;
-      w.x_vec = row_aligned(im, 4) ? 1 : 0;
+      w.x_vec = row_aligned(im, 16) ? 1 : 0;
       w.g_vec = row_aligned(gout, g32 ? 32 : 16) ? 1 : 0;
-      w.n_units = im.n * chunks;
-      const dim3 grid(static_cast<uint32_t>(w.n_units)), block(kThreads);
+      w.n_tiles = n_tiles;
+      w.units = units;
+      const dim3 grid(static_cast<uint32_t>(units)), block(kThreads);
       switch (pr.k) {
         case 1:
           if (g32) hipLaunchKernelGGL((k_bank_wgrad<1, float>), grid, block, 0, s, w);
@@ -792,10 +932,8 @@ f2d_status bank_backward_bf16(const Problem& pr, const f2d_tensor& gout, const f
       if (e != hipSuccess) return hip_status(e, "bf16 bank wgrad launch");
     }
     // partial layout [unit][f][K*K] == reduce layout with nrep = units, chunks = 1
-    hipError_t e = launch_reduce_partials(
-        reinterpret_cast<const float*>(static_cast<const char*>(ws) + bank_frame_bytes(pr)), grad_filter, nf,
-        pr.k * pr.k,
-                                          empty ? 0 : im.n * chunks, 1, s);
+    hipError_t e = launch_reduce_partials(reinterpret_cast<float*>(static_cast<char*>(ws) + bank_frame_bytes(pr)),
+                                          grad_filter, nf, pr.k * pr.k, empty ? 0 : units, 1, s);
     if (e != hipSuccess) return hip_status(e, "bf16 bank reduce launch");
   }
   return ok();

@@ -18,8 +18,8 @@
 // X tile with its clamped halo in LDS, keeps its 4 x 4 block of G-bar in
 // registers and accumulates all K*K tap sums per thread; a fixed butterfly
 // across each wave and a fixed-order sum across the 4 waves leave one
-// partial per tap, written to the workspace.  k_reduce_partials then adds the
-// partials of each filter tap in a fixed order, so the result is the same
+// partial per tap, written to the workspace.  The reduction kernels then add
+// the partials of each filter tap in a fixed order, so the result is the same
 // bits on every run.
 #include <hip/hip_bf16.h>
 #include <hip/hip_runtime.h>
@@ -335,18 +335,58 @@ __global__ __launch_bounds__(kThreads) void k_grad_filter_generic(GradFilterPara
 
 // out[f][e] = sum over (rep, chunk) of partial[((rep*nf + f)*chunks + chunk)][e],
 // each thread summing a fixed stride of units, then a fixed butterfly.
-__global__ __launch_bounds__(256) void k_reduce_partials(const float* __restrict__ partial,
-                                                         float* __restrict__ out, int64_t nf, int kk,
-                                                         int64_t nrep, int64_t chunks) {
+// Fixed-order reduction of the partial sets, in two passes over the layout
+// partial[((rep * nf + f) * chunks + c) * kk + e] (item i = rep * chunks + c):
+//  pass 1  thread (j = f*kk + e, segment s) adds items s*L .. s*L+L-1 in
+//          order and writes the sum over item s*L (it alone reads that slot);
+//  pass 2  adds the segment sums in order: one thread per output when there
+//          are many outputs, else one work-group per output (strided
+//          threads, then a fixed shuffle tree).
+__device__ __forceinline__ int64_t partial_index(int64_t i, int64_t f, int e, int64_t nf, int kk, int64_t chunks) {
+  const int64_t rep = i / chunks, c = i - rep * chunks;
+  return ((rep * nf + f) * chunks + c) * kk + e;
+}
+
+__global__ __launch_bounds__(256) void k_reduce_segments(float* __restrict__ partial, int64_t nf, int kk,
+                                                         int64_t chunks, int64_t count, int64_t seg) {
+  const int64_t j = static_cast<int64_t>(blockIdx.x) * 256 + threadIdx.x;
+  if (j >= nf * kk) return;
+  const int64_t f = j / kk;
+  const int e = static_cast<int>(j - f * kk);
+  const int64_t i0 = static_cast<int64_t>(blockIdx.y) * seg;
+  const int64_t i1 = i0 + seg < count ? i0 + seg : count;
+  float s = 0.0f;
+  int64_t i = i0;
+  for (; i + 4 <= i1; i += 4) {
+    const float a0 = partial[partial_index(i, f, e, nf, kk, chunks)];
+    const float a1 = partial[partial_index(i + 1, f, e, nf, kk, chunks)];
+    const float a2 = partial[partial_index(i + 2, f, e, nf, kk, chunks)];
+    const float a3 = partial[partial_index(i + 3, f, e, nf, kk, chunks)];
+    s = (((s + a0) + a1) + a2) + a3;
+  }
+  for (; i < i1; ++i) s += partial[partial_index(i, f, e, nf, kk, chunks)];
+  partial[partial_index(i0, f, e, nf, kk, chunks)] = s;
+}
+
+__global__ __launch_bounds__(256) void k_reduce_columns(const float* __restrict__ partial, float* __restrict__ out,
+                                                        int64_t nf, int kk, int64_t chunks, int64_t nseg,
+                                                        int64_t seg) {
+  const int64_t j = static_cast<int64_t>(blockIdx.x) * 256 + threadIdx.x;
+  if (j >= nf * kk) return;
+  const int64_t f = j / kk;
+  const int e = static_cast<int>(j - f * kk);
+  float s = 0.0f;
+  for (int64_t g = 0; g < nseg; ++g) s += partial[partial_index(g * seg, f, e, nf, kk, chunks)];
+  out[j] = s;
+}
+
+__global__ __launch_bounds__(256) void k_reduce_rows(const float* __restrict__ partial, float* __restrict__ out,
+                                                     int64_t nf, int kk, int64_t chunks, int64_t nseg, int64_t seg) {
   __shared__ float red[4];
   const int64_t f = blockIdx.x / kk;
   const int e = static_cast<int>(blockIdx.x % kk);
-  const int64_t count = nrep * chunks;
   float s = 0.0f;
-  for (int64_t i = threadIdx.x; i < count; i += 256) {
-    const int64_t rep = i / chunks, c = i - rep * chunks;
-    s += partial[((rep * nf + f) * chunks + c) * kk + e];
-  }
+  for (int64_t g = threadIdx.x; g < nseg; g += 256) s += partial[partial_index(g * seg, f, e, nf, kk, chunks)];
 #pragma unroll
   for (int off = 32; off >= 1; off >>= 1) s += __shfl_xor(s, off, 64);
   if (threadIdx.x % 64 == 0) red[threadIdx.x / 64] = s;
@@ -399,12 +439,26 @@ hipError_t launch_grad_filter_generic(const GradFilterParams& p, int K, hipStrea
   return hipGetLastError();
 }
 
-hipError_t launch_reduce_partials(const float* partial, float* out, int64_t nf, int kk, int64_t nrep,
-                                  int64_t chunks, hipStream_t s) {
-  const int64_t blocks = nf * kk;
-  if (blocks <= 0) return hipSuccess;
-  hipLaunchKernelGGL(k_reduce_partials, dim3(static_cast<uint32_t>(blocks)), dim3(256), 0, s, partial, out,
-                     nf, kk, nrep, chunks);
+hipError_t launch_reduce_partials(float* partial, float* out, int64_t nf, int kk, int64_t nrep, int64_t chunks,
+                                  hipStream_t s) {
+  const int64_t m = nf * kk;  // outputs
+  if (m <= 0) return hipSuccess;
+  const int64_t count = nrep * chunks;
+  constexpr int64_t kSeg = 32;  // items per first-pass segment
+  const int64_t nseg = (count + kSeg - 1) / kSeg;
+  const int64_t col_blocks = (m + 255) / 256;
+  if (nseg > 0) {
+    hipLaunchKernelGGL(k_reduce_segments, dim3(static_cast<uint32_t>(col_blocks), static_cast<uint32_t>(nseg)),
+                       dim3(256), 0, s, partial, nf, kk, chunks, count, kSeg);
+    hipError_t e = hipGetLastError();
+    if (e != hipSuccess) return e;
+  }
+  if (m >= 4096 || nseg <= 64)
+    hipLaunchKernelGGL(k_reduce_columns, dim3(static_cast<uint32_t>(col_blocks)), dim3(256), 0, s, partial, out,
+                       nf, kk, chunks, nseg, kSeg);
+  else
+    hipLaunchKernelGGL(k_reduce_rows, dim3(static_cast<uint32_t>(m)), dim3(256), 0, s, partial, out, nf, kk,
+                       chunks, nseg, kSeg);
   return hipGetLastError();
 }
 

@@ -57,7 +57,9 @@ constexpr int kEdgeF32 = 0;
 hipError_t launch_grad_input_edges(const EdgeParams& p, int kind, hipStream_t s);
 hipError_t launch_grad_filter_f32(const GradFilterParams& p, int K, hipStream_t s);
 hipError_t launch_grad_filter_generic(const GradFilterParams& p, int K, hipStream_t s);
-hipError_t launch_reduce_partials(const float* partial, float* out, int64_t nf, int kk, int64_t nrep,
+// Sums the partials over items (rep, chunk) in a fixed order; overwrites
+// some partial slots with intermediate sums.
+hipError_t launch_reduce_partials(float* partial, float* out, int64_t nf, int kk, int64_t nrep,
                                   int64_t chunks, hipStream_t s);
 TileShape grad_filter_tile();
 

@@ -83,6 +83,19 @@ def test_gaussian_data_error_vs_fp64(gpu_lib, k):
     assert oracle.rel_l2(host(gf), oracle.grad_filter(x, g, f.shape, "bank")) <= 1e-2
 
 
+@pytest.mark.parametrize("k", [1, 3, 5])
+def test_forward_wide_input_bank(gpu_lib, k):
+    """33..64 input channels (eight channel groups) with 20 outputs: the widest
+    forward tile shape that fits the weights and source tile in LDS."""
+    r = wl.rng(34, k)
+    x = r.integers(-8, 9, (2, 40, 21, 70)).astype(np.float32)
+    f = r.integers(-8, 9, (20, 40, k, k)).astype(np.float32)
+    xd, xv = bf(x)
+    fd, fv = bf(f)
+    y = gpu_lib.forward(xd, fd, mode="bank")
+    assert np.array_equal(host(y), oracle.forward(xv, fv, "bank"))
+
+
 def test_bf16_bank_rows_band(gpu_lib):
     k = 5
     r = wl.rng(32)
