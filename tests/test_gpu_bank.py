@@ -36,6 +36,15 @@ def host(t):
     return t.double().cpu().numpy()
 
 
+def assert_same(got, want):
+    """Bit-for-bit equality; on failure name the mismatching positions."""
+    bad = np.argwhere(got != want)
+    assert len(bad) == 0, (f"{len(bad)} of {got.size} differ; first at "
+                           f"{[tuple(int(v) for v in b) for b in bad[:8]]}: "
+                           f"got {[float(got[tuple(b)]) for b in bad[:8]]}, "
+                           f"want {[float(want[tuple(b)]) for b in bad[:8]]}")
+
+
 CASES = [(2, 3, 4, 37, 70), (1, 16, 64, 20, 65), (2, 16, 16, 9, 130), (1, 8, 20, 33, 64),
          (1, 1, 1, 1, 1), (1, 16, 64, 3, 5)]
 
@@ -52,11 +61,11 @@ def test_integer_operands_are_bit_exact(gpu_lib, case, k):
     fd, fv = bf(f)
     y = gpu_lib.forward(xd, fd, mode="bank")
     assert y.dtype == torch.float32
-    assert np.array_equal(host(y), oracle.forward(xv, fv, "bank"))
+    assert_same(host(y), oracle.forward(xv, fv, "bank"))
     for gdev in (bf(g)[0], f32(g)):  # bf16 or f32 upstream gradient (f32 is rounded inside)
         gi, gf = gpu_lib.backward(xd, fd, gdev, mode="bank")
-        assert np.array_equal(host(gi), oracle.grad_input(g, fv, x.shape, "bank"))
-        assert np.array_equal(host(gf), oracle.grad_filter(xv, g, f.shape, "bank"))
+        assert_same(host(gi), oracle.grad_input(g, fv, x.shape, "bank"))
+        assert_same(host(gf), oracle.grad_filter(xv, g, f.shape, "bank"))
 
 
 @pytest.mark.parametrize("k", [3, 5])
@@ -93,7 +102,7 @@ def test_forward_wide_input_bank(gpu_lib, k):
     xd, xv = bf(x)
     fd, fv = bf(f)
     y = gpu_lib.forward(xd, fd, mode="bank")
-    assert np.array_equal(host(y), oracle.forward(xv, fv, "bank"))
+    assert_same(host(y), oracle.forward(xv, fv, "bank"))
 
 
 def test_bf16_bank_rows_band(gpu_lib):
