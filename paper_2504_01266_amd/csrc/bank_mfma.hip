@@ -101,7 +101,7 @@ struct ConvGeom {
   // channels-last pixel stride padded by 16 bytes: 16 lanes reading 16 bytes
   // at consecutive pixels then cover all 64 LDS banks exactly once
   static constexpr int PS = CI8 + 8;
-  static constexpr int S_ELEMS = LH * LW * PS + 8;  // + one zero 16-byte slot
+  static constexpr int S_ELEMS = LH * LW * PS;      // one source tile (16-byte multiple)
   static constexpr int W_ELEMS = OT * 16 * WSTR;
   // weights + two source tiles when they fit in LDS (160 KiB), else one
   static constexpr int NBUF = (W_ELEMS + 2 * S_ELEMS) * 2 <= 160 * 1024 ? 2 : 1;
@@ -339,10 +339,6 @@ __global__ __launch_bounds__(kConvThreads) void k_bank_conv(BankParams p) {
   decode(t, n, og, oy0, ox0);
   Raw<TS, G::NT> st;
   stage_load<G, K, CG, TS>(p, n, oy0, ox0, wave, lane, st);
-  if (tid < 8) {  // zero slot of each source buffer (never overwritten)
-    sl0[G::S_ELEMS - 8 + tid] = 0;
-    if (G::NBUF == 2) sl0[2 * G::S_ELEMS - 8 + tid] = 0;
-  }
   load_weights<G, K, OT, CG, ADJ>(p, og, tid, wl);
   stage_store<G, K, CG, ADJ, TS>(p, oy0, ox0, wave, lane, st, sl0);
   __syncthreads();
@@ -373,10 +369,16 @@ __global__ __launch_bounds__(kConvThreads) void k_bank_conv(BankParams p) {
       bf16x8 wf[OT], xf[HP];
 #pragma unroll
       for (int a = 0; a < OT; ++a) wf[a] = *reinterpret_cast<const bf16x8*>(w_lane + a * 16 * G::WSTR + 32 * s);
+      // b_step_offset clamps taps past K*K to tap 0, so every read is of
+      // staged pixels; quarters holding a padded k-group (past KG, only in
+      // the last step) zero their operand in registers
       const uint16_t* bp = b_lane + b_step_offset<G, K, CG>(s, hsel, q);
-      if (4 * s + 3 >= G::KG && 4 * s + q >= G::KG) bp = sl + (G::S_ELEMS - 8);  // padded k-group
+      const bool pad = 4 * s + 3 >= G::KG && 4 * s + q >= G::KG;
 #pragma unroll
-      for (int b = 0; b < HP; ++b) xf[b] = *reinterpret_cast<const bf16x8*>(bp + b * 16 * G::PS);
+      for (int b = 0; b < HP; ++b) {
+        xf[b] = *reinterpret_cast<const bf16x8*>(bp + b * 16 * G::PS);
+        if (pad) xf[b] = bf16x8{};
+      }
 #pragma unroll
       for (int a = 0; a < OT; ++a)
 #pragma unroll

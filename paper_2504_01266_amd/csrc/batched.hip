@@ -32,34 +32,54 @@ __global__ __launch_bounds__(kThreads) void k_batched_f32(const f2d_batch_item* 
   const int tx = threadIdx.x % kTX;
   const int ty = threadIdx.x / kTX;
 
-  for (int64_t t = blockIdx.x; t < total_tiles; t += gridDim.x) {
-    // owning item: the last i with prefix[i] <= t
-    int lo = 0, hi = n_items;
+  // Tiles are taken in increasing order, so the owning item only moves
+  // forward: one binary search for the first tile, then a forward step; the
+  // item and its taps are reloaded only when it changes.
+  int64_t t = blockIdx.x;
+  if (t >= total_tiles) return;
+  int lo = 0;
+  {
+    int hi = n_items;  // the last i with prefix[i] <= t
     while (hi - lo > 1) {
       const int mid = (lo + hi) / 2;
       if (prefix[mid] <= t) lo = mid; else hi = mid;
     }
-    // the search ran on uniform values; say so, so that the item and its taps
-    // are fetched with scalar loads into scalar registers
-    lo = __builtin_amdgcn_readfirstlane(lo);
-    const f2d_batch_item it = items[lo];
-    const int64_t local = t - prefix[lo];
-    const int64_t tiles_x = (it.w + G::TW - 1) / G::TW;
-    const int64_t tiles_y = (it.h + G::TH - 1) / G::TH;
-    const int64_t per_plane = tiles_x * tiles_y;
-    const int64_t c = local / per_plane;
-    const int64_t r = local - c * per_plane;
-    const int64_t tile_y = r / tiles_x;
-    const int64_t tile_x = r - tile_y * tiles_x;
-    const int64_t oy0 = tile_y * G::TH, ox0 = tile_x * G::TW;
-
-    const float* sp = static_cast<const float*>(it.image) + c * it.in_stride_c;
-    stage_tile<K, PX, PY, false>(lds, sp, it.in_stride_h, it.h, it.w, oy0, ox0);
-    float tap[1][K * K];
+  }
+  // the search ran on uniform values; say so, so that the item and its taps
+  // are fetched with scalar loads into scalar registers
+  lo = __builtin_amdgcn_readfirstlane(lo);
+  f2d_batch_item it;
+  int64_t next_start;
+  float tap[1][K * K];
+  int64_t start;
+  uint32_t tiles_x, per_plane;  // one item has fewer than 2^32 tiles
+  auto load_item = [&]() {
+    it = items[lo];
+    start = prefix[lo];
+    next_start = prefix[lo + 1];
+    tiles_x = static_cast<uint32_t>((it.w + G::TW - 1) / G::TW);
+    per_plane = tiles_x * static_cast<uint32_t>((it.h + G::TH - 1) / G::TH);
     const float* fp = static_cast<const float*>(it.filter);
 #pragma unroll
     for (int e = 0; e < K * K; ++e)
       tap[0][e] = __int_as_float(__builtin_amdgcn_readfirstlane(__float_as_int(fp[e])));
+  };
+  load_item();
+  for (; t < total_tiles; t += gridDim.x) {
+    if (t >= next_start) {
+      while (lo + 1 < n_items && prefix[lo + 1] <= t) ++lo;
+      lo = __builtin_amdgcn_readfirstlane(lo);
+      load_item();
+    }
+    const uint32_t local = static_cast<uint32_t>(t - start);
+    const uint32_t c = local / per_plane;
+    const uint32_t r = local - c * per_plane;
+    const uint32_t tile_y = r / tiles_x;
+    const uint32_t tile_x = r - tile_y * tiles_x;
+    const int64_t oy0 = static_cast<int64_t>(tile_y) * G::TH, ox0 = static_cast<int64_t>(tile_x) * G::TW;
+
+    const float* sp = static_cast<const float*>(it.image) + c * it.in_stride_c;
+    stage_tile<K, PX, PY, false>(lds, sp, it.in_stride_h, it.h, it.w, oy0, ox0);
     float acc[1][PY][PX];
 #pragma unroll
     for (int jy = 0; jy < PY; ++jy)

@@ -125,7 +125,7 @@ __global__ __launch_bounds__(kThreads) void k_stencil_f32(StencilParams p) {
       sp = static_cast<const float*>(p.src[0]) + n * p.src_sn[0] + ch * p.src_sc[0];
       sh = p.src_sh[0];
     }
-    stage_tile<K, PX, PY, ADJ>(lds, sp, sh, p.H, p.W, p.row0 + oy0, ox0);
+    stage_tile<K, PX, PY, ADJ, NOUT == 1>(lds, sp, sh, p.H, p.W, p.row0 + oy0, ox0);
 
     float tap[NOUT][K * K];
 #pragma unroll

@@ -77,12 +77,17 @@ __device__ __forceinline__ float* dst_plane(const StencilParams& p, int t, int64
 }
 
 // Stage one source plane's tile (source rows row_base-R.., columns
-// col_base-R..) in LDS.  Waves take whole rows, so a row's address is uniform
-// and lives in scalar registers; lanes take columns, and each lane's clamped
+// col_base-R..) in LDS.  Waves take whole rows (one row address per wave);
+// lanes take columns, and each lane's clamped
 // (or zero-masked) column offset is computed once for every row.  All of a
 // wave's loads are issued into registers before the first LDS write, so the
 // wave waits on memory once per tile instead of once per row.
-template <int K, int PX, int PY, bool ADJ>
+//
+// UNI: take the wave index as uniform, so that row indices, clamps and row
+// addresses are scalar and each load is scalar base + 32-bit lane offset.
+// This shortens single-output kernels; kernels that stage many source planes
+// per tile keep the per-lane form, which measured faster there.
+template <int K, int PX, int PY, bool ADJ, bool UNI = true>
 __device__ __forceinline__ void stage_tile(float* __restrict__ lds, const float* __restrict__ sp,
                                            int64_t sh, int64_t H, int64_t W, int64_t row_base,
                                            int64_t col_base) {
@@ -92,8 +97,9 @@ __device__ __forceinline__ void stage_tile(float* __restrict__ lds, const float*
   constexpr int CPL = (G::LW + kWaveLanes - 1) / kWaveLanes;  // column chunks per lane
   constexpr int RPW = (G::LH + kWaves - 1) / kWaves;          // rows per wave
   const int lane = threadIdx.x % kWaveLanes;
-  const int wave = threadIdx.x / kWaveLanes;
-  int coff[CPL];
+  const int wave = UNI ? __builtin_amdgcn_readfirstlane(threadIdx.x / kWaveLanes)
+                       : static_cast<int>(threadIdx.x / kWaveLanes);
+  uint32_t coff[CPL];
   bool cval[CPL];
 #pragma unroll
   for (int j = 0; j < CPL; ++j) {
@@ -101,10 +107,10 @@ __device__ __forceinline__ void stage_tile(float* __restrict__ lds, const float*
     const int64_t gx = col_base - G::R + lx;
     if constexpr (ADJ) {
       cval[j] = gx >= 0 && gx < W;
-      coff[j] = cval[j] ? static_cast<int>(gx) : 0;
+      coff[j] = cval[j] ? static_cast<uint32_t>(gx) : 0u;
     } else {
       cval[j] = true;
-      coff[j] = static_cast<int>(gx < 0 ? 0 : (gx >= W ? W - 1 : gx));
+      coff[j] = static_cast<uint32_t>(gx < 0 ? 0 : (gx >= W ? W - 1 : gx));
     }
   }
   float buf[RPW][CPL];
