@@ -134,7 +134,15 @@ def cpu_baseline(oracle, x, f, outs, budget_s):
     t0 = time.perf_counter()
     ref = oracle.forward_int(x64, f64, "depthwise", rows=(0, rows))
     dt = time.perf_counter() - t0
-    value = c * rows * w * 18 / dt / 1e6
+    passes = 1
+    if rows == h:  # the whole frame is shorter than the budget: repeat it
+        extra = int(min(200, max(0, budget_s / max(dt, 1e-3) - 1)))
+        t1 = time.perf_counter()
+        for _ in range(extra):
+            oracle.forward_int(x64, f64, "depthwise", rows=(0, rows))
+        dt += time.perf_counter() - t1
+        passes += extra
+    value = passes * c * rows * w * 18 / dt / 1e6
     gx = outs[0][:, :, :rows].cpu().numpy()
     gy = outs[1][:, :, :rows].cpu().numpy()
     mm = outs[2][:, :, :rows].cpu().numpy()
@@ -143,7 +151,7 @@ def cpu_baseline(oracle, x, f, outs, budget_s):
     return {"value": round(value, 2), "unit": "Mpix*taps/s", "cores": oracle.num_threads(),
             "kind": "oracle", "seconds": round(dt, 2),
             "sample": f"output rows 0..{rows - 1} of all 3 channels of the 8K frame "
-                      f"({rows}/{h} rows, int64 direct loops, OpenMP over rows)"}, \
+                      f"({rows}/{h} rows, {passes} pass(es), int64 direct loops, OpenMP over rows)"}, \
         {"rows_checked": rows, "mismatches": mism}
 
 
