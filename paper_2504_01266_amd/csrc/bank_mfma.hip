@@ -66,6 +66,7 @@ struct BankParams {
   int64_t frame_plane;
   int32_t fr;
   int32_t d_vec;  // output rows and planes 16-byte (f32) / 8-byte (bf16) aligned
+  int32_t s_vec;  // source rows and planes 16-byte aligned and W % 8 == 0 (vector staging)
 };
 
 __device__ __forceinline__ uint16_t f32_to_bf16_bits(float f) {
@@ -97,7 +98,11 @@ struct ConvGeom {
   static constexpr int WSTR = KP + 8;        // weight row stride (elements), staggers banks
   static constexpr int TW = 16 * PT;
   static constexpr int LH = kTH + K - 1;
-  static constexpr int LW = TW + K - 1;
+  // staged columns x0-8 .. x0+TW+7: 16-byte aligned 8-column chunks (R <= 8);
+  // output pixel px, tap column v reads LDS column px + XOFF + v
+  static constexpr int LW = TW + 16;
+  static constexpr int XOFF = 8 - R;
+  static constexpr int CHUNKS = LW / 8;
   // channels-last pixel stride padded by 16 bytes: 16 lanes reading 16 bytes
   // at consecutive pixels then cover all 64 LDS banks exactly once
   static constexpr int PS = CI8 + 8;
@@ -106,121 +111,220 @@ struct ConvGeom {
   // weights + two source tiles when they fit in LDS (160 KiB), else one
   static constexpr int NBUF = (W_ELEMS + 2 * S_ELEMS) * 2 <= 160 * 1024 ? 2 : 1;
   static constexpr int LDS_ELEMS = W_ELEMS + NBUF * S_ELEMS;
-  static constexpr int HALO_LANES = LH * CG * (K - 1);  // staging tasks of the halo columns
-  static constexpr int TASKS = LH * CG + (HALO_LANES + 63) / 64;
-  static constexpr int NT = (TASKS + kConvWaves - 1) / kConvWaves;  // staging tasks per wave
+  // staging units (row, channel group, 8-column chunk), 8 per wave instruction
+  static constexpr int UNITS = LH * CG * CHUNKS;
+  static constexpr int NT = (UNITS + 8 * kConvWaves - 1) / (8 * kConvWaves);  // per wave
+  static_assert(R <= 8, "K <= 17");
 };
 
-// Staging of the source tile, channels-last.  Task = (row ly, channel group
-// cg) over the TW main columns (one lane per column), plus tasks that cover
-// the K-1 halo columns of every (row, group).  A lane loads the 8 channels
-// of its pixel (one load per channel plane, coalesced across the lanes of a
-// row) and later writes them as one 16-byte LDS store.  Loads always use
-// clamped, valid addresses; the border rule (clamp, or zero for the
-// adjoint) and channel padding are applied when the values are packed.
-template <int K, int CG, int LH, int TW>
-__device__ __forceinline__ void task_pos(int task, int lane, int& ly, int& cg, int& lx, bool& act) {
-  constexpr int KH = K - 1 > 0 ? K - 1 : 1;
-  if (task < LH * CG) {
-    ly = task / CG;
-    cg = task - ly * CG;
-    lx = lane;
-    act = lane < TW;
-  } else {
-    const int hl = (task - LH * CG) * 64 + lane;
-    act = hl < LH * CG * (K - 1);
-    const int h = act ? hl : 0;
-    lx = TW + h % KH;
-    const int rest = h / KH;
-    ly = rest % LH;
-    cg = rest / LH;
-  }
+// Staging of the source tile, channels-last.  A unit = (row ly, channel
+// group cg, 8-column chunk) is handled by 8 lanes: lane j loads the chunk's
+// 8 pixels of channel cg*8 + j (one 16-byte load in the interior, clamped
+// element loads at the left and right image edges), and after an 8 x 8
+// transpose across the 8 lanes it holds the 8 channels of pixel j, which it
+// writes as one 16-byte LDS store.  Loads always use valid addresses; the
+// border rule (clamp, or zero for the adjoint) and the channel padding are
+// applied to the values.
+template <typename G, int CG>
+__device__ __forceinline__ void unit_pos(int it, int wave, int lane, int& ly, int& cg, int& chunk, bool& act) {
+  const int u = (it * kConvWaves + wave) * 8 + (lane >> 3);
+  act = u < G::UNITS;
+  const int uu = act ? u : 0;
+  chunk = uu % G::CHUNKS;
+  const int rest = uu / G::CHUNKS;
+  cg = rest % CG;
+  ly = rest / CG;
 }
 
-// Raw staged values of one tile for this wave, one register per value (bf16
-// sources zero-extended, f32 sources rounded to bf16 when packed).  Packing
-// happens only in stage_store, after the MFMA loop, so the loads stay in
-// flight while the matrix cores work on the current tile.
+// Raw staged values of one tile for this wave: 8 consecutive pixels of one
+// channel per unit (bf16 pairs, or f32 rounded to bf16 when packed).  The
+// transpose and LDS write happen only in stage_store, after the MFMA loop,
+// so interior loads stay in flight while the matrix cores work.
 template <typename TS, int NT>
 struct Raw;
 template <int NT>
 struct Raw<uint16_t, NT> {
-  uint32_t v[NT][8];
-  __device__ __forceinline__ uint32_t get(int it, int c) const { return v[it][c]; }
-  __device__ __forceinline__ void load(int it, int c, const uint16_t* a) { v[it][c] = *a; }
+  u32x4 v[NT];
+  __device__ __forceinline__ u32x4 pairs(int it) const { return v[it]; }
 };
 template <int NT>
 struct Raw<float, NT> {
   float v[NT][8];
-  __device__ __forceinline__ uint32_t get(int it, int c) const { return f32_to_bf16_bits(v[it][c]); }
-  __device__ __forceinline__ void load(int it, int c, const float* a) { v[it][c] = *a; }
+  __device__ __forceinline__ u32x4 pairs(int it) const {
+    u32x4 r;
+#pragma unroll
+    for (int d = 0; d < 4; ++d)
+      r[d] = static_cast<uint32_t>(f32_to_bf16_bits(v[it][2 * d])) |
+             (static_cast<uint32_t>(f32_to_bf16_bits(v[it][2 * d + 1])) << 16);
+    return r;
+  }
 };
 
-template <typename G, int K, int CG, typename TS>
-__device__ __forceinline__ void stage_load(const BankParams& p, int64_t n, int64_t oy0, int64_t ox0,
-                                           int wave, int lane, Raw<TS, G::NT>& st) {
-  const TS* sp = static_cast<const TS*>(p.src) + n * p.s_sn;
+// 8 consecutive elements from a 16-byte aligned address
+__device__ __forceinline__ void load_vec(const uint16_t* a, u32x4& out) { out = *reinterpret_cast<const u32x4*>(a); }
+__device__ __forceinline__ void load_vec(const float* a, float (&out)[8]) {
+  const float4 x = reinterpret_cast<const float4*>(a)[0];
+  const float4 y = reinterpret_cast<const float4*>(a)[1];
+  out[0] = x.x;
+  out[1] = x.y;
+  out[2] = x.z;
+  out[3] = x.w;
+  out[4] = y.x;
+  out[5] = y.y;
+  out[6] = y.z;
+  out[7] = y.w;
+}
+
+// 8 consecutive elements of a row starting at column gx0 from element loads
+// at clamped columns (zero outside the row for the adjoint): unaligned rows
+// or widths that are not a multiple of 8.
+template <bool ADJ>
+__device__ __forceinline__ void load_chunk(const uint16_t* row, int64_t gx0, int64_t W, u32x4& out) {
+  {
+    uint32_t h[8];
 #pragma unroll
-  for (int it = 0; it < G::NT; ++it) {
-    const int task = wave + kConvWaves * it;
-    if (task < G::LH * CG) {
-      // main task: uniform row and channel group, one column per lane; the
-      // channel planes are scalar bases, the column a 32-bit lane offset
-      const int ly = task / CG, cg = task - (task / CG) * CG;
-      int64_t gy = p.row0 + oy0 - G::R + ly;
-      gy = gy < 0 ? 0 : (gy >= p.H ? p.H - 1 : gy);
-      int64_t gx = ox0 - G::R + lane;
-      gx = gx < 0 ? 0 : (gx >= p.W ? p.W - 1 : gx);
-      const TS* row = sp + gy * p.s_sh;
-      const uint32_t off = static_cast<uint32_t>(gx);
+    for (int e = 0; e < 8; ++e) {
+      const int64_t x = gx0 + e;
+      const int64_t cx = x < 0 ? 0 : (x >= W ? W - 1 : x);
+      const uint32_t v = row[cx];
+      h[e] = (ADJ && (x < 0 || x >= W)) ? 0u : v;
+    }
+    out = u32x4{h[0] | (h[1] << 16), h[2] | (h[3] << 16), h[4] | (h[5] << 16), h[6] | (h[7] << 16)};
+  }
+}
+template <bool ADJ>
+__device__ __forceinline__ void load_chunk(const float* row, int64_t gx0, int64_t W, float (&out)[8]) {
+  {
 #pragma unroll
-      for (int c = 0; c < 8; ++c) {
-        const int ch = cg * 8 + c < p.CI ? cg * 8 + c : p.CI - 1;
-        st.load(it, c, row + ch * p.s_sc + off);
-      }
-    } else {
-      const int tk = task < G::TASKS ? task : 0;
-      int ly, cg, lx;
-      bool act;
-      task_pos<K, CG, G::LH, G::TW>(tk, lane, ly, cg, lx, act);
-      int64_t gy = p.row0 + oy0 - G::R + ly, gx = ox0 - G::R + lx;
-      gy = gy < 0 ? 0 : (gy >= p.H ? p.H - 1 : gy);
-      gx = gx < 0 ? 0 : (gx >= p.W ? p.W - 1 : gx);
-      const TS* px = sp + gy * p.s_sh + gx;
-#pragma unroll
-      for (int c = 0; c < 8; ++c) {
-        const int ch = cg * 8 + c < p.CI ? cg * 8 + c : p.CI - 1;
-        st.load(it, c, px + ch * p.s_sc);
-      }
+    for (int e = 0; e < 8; ++e) {
+      const int64_t x = gx0 + e;
+      const int64_t cx = x < 0 ? 0 : (x >= W ? W - 1 : x);
+      const float v = row[cx];
+      out[e] = (ADJ && (x < 0 || x >= W)) ? 0.0f : v;
     }
   }
 }
 
 template <typename G, int K, int CG, bool ADJ, typename TS>
-__device__ __forceinline__ void stage_store(const BankParams& p, int64_t oy0, int64_t ox0, int wave, int lane,
-                                            const Raw<TS, G::NT>& st, uint16_t* __restrict__ sl) {
+__device__ __forceinline__ void stage_load(const BankParams& p, int64_t n, int64_t oy0, int64_t ox0,
+                                           int wave, int lane, Raw<TS, G::NT>& st) {
+  const TS* sp = static_cast<const TS*>(p.src) + n * p.s_sn;
+  const int j = lane & 7;
+  const bool vec = p.s_vec != 0;
 #pragma unroll
   for (int it = 0; it < G::NT; ++it) {
-    const int task = wave + kConvWaves * it;
-    if (task >= G::TASKS) break;
-    int ly, cg, lx;
+    int ly, cg, chunk;
     bool act;
-    task_pos<K, CG, G::LH, G::TW>(task, lane, ly, cg, lx, act);
-    if (!act) continue;
-    bool valid = true;
-    if constexpr (ADJ) {
-      const int64_t gy = p.row0 + oy0 - G::R + ly, gx = ox0 - G::R + lx;
-      valid = gy >= 0 && gy < p.H && gx >= 0 && gx < p.W;
+    unit_pos<G, CG>(it, wave, lane, ly, cg, chunk, act);
+    int64_t gy = p.row0 + oy0 - G::R + ly;
+    gy = gy < 0 ? 0 : (gy >= p.H ? p.H - 1 : gy);
+    const int c = cg * 8 + j;
+    const TS* row = sp + static_cast<int64_t>(c < p.CI ? c : p.CI - 1) * p.s_sc + gy * p.s_sh;
+    const int64_t gx0 = ox0 - 8 + 8 * chunk;
+    if (vec) {
+      // aligned rows, W a multiple of 8: every chunk lies left of, inside or
+      // right of the row, so one 16-byte load of the nearest chunk inside it
+      // always serves; stage_store fixes up the outside chunks
+      const int64_t gxl = gx0 < 0 ? 0 : (gx0 > p.W - 8 ? p.W - 8 : gx0);
+      load_vec(row + gxl, st.v[it]);
+    } else {
+      load_chunk<ADJ>(row, gx0, p.W, st.v[it]);
     }
-    uint32_t w[4];
+  }
+}
+
+// Value of lane j ^ m (m = 1, 2, 4) by DPP: quad permutations for 1 and 2,
+// row shifts by 4 lanes (select by bit 2 of the lane) for 4.
+template <int M>
+__device__ __forceinline__ uint32_t lane_xor(uint32_t v, int j) {
+  const int x = static_cast<int>(v);
+  if constexpr (M == 1) {
+    return static_cast<uint32_t>(__builtin_amdgcn_update_dpp(x, x, 0xB1, 0xF, 0xF, false));  // [1,0,3,2]
+  } else if constexpr (M == 2) {
+    return static_cast<uint32_t>(__builtin_amdgcn_update_dpp(x, x, 0x4E, 0xF, 0xF, false));  // [2,3,0,1]
+  } else {
+    const int up = __builtin_amdgcn_update_dpp(x, x, 0x104, 0xF, 0xF, false);    // row_shl:4 (lane + 4)
+    const int down = __builtin_amdgcn_update_dpp(x, x, 0x114, 0xF, 0xF, false);  // row_shr:4 (lane - 4)
+    return static_cast<uint32_t>((j & 4) ? down : up);
+  }
+}
+
+// 8 x 8 transpose of 16-bit values across the 8 lanes of a unit: element i
+// of lane j (pair i/2, low half for even i) becomes element j of lane i.
+// Three exchanges, with lanes j^4 (two pairs), j^2 (one pair) and j^1
+// (half a pair).
+__device__ __forceinline__ u32x4 transpose8(u32x4 d, int j) {
+  auto xr = [j](uint32_t v, int m) {
+    return m == 4 ? lane_xor<4>(v, j) : (m == 2 ? lane_xor<2>(v, j) : lane_xor<1>(v, j));
+  };
+  {
+    const bool b = (j & 4) != 0;
+    const uint32_t r0 = xr(b ? d[0] : d[2], 4), r1 = xr(b ? d[1] : d[3], 4);
+    if (b) {
+      d[0] = r0;
+      d[1] = r1;
+    } else {
+      d[2] = r0;
+      d[3] = r1;
+    }
+  }
+  {
+    const bool b = (j & 2) != 0;
+    const uint32_t r0 = xr(b ? d[0] : d[1], 2), r1 = xr(b ? d[2] : d[3], 2);
+    if (b) {
+      d[0] = r0;
+      d[2] = r1;
+    } else {
+      d[1] = r0;
+      d[3] = r1;
+    }
+  }
+  {
+    const bool b = (j & 1) != 0;
+    const uint32_t s0 = b ? ((d[0] & 0xffffu) | (d[1] << 16)) : ((d[0] >> 16) | (d[1] & 0xffff0000u));
+    const uint32_t s1 = b ? ((d[2] & 0xffffu) | (d[3] << 16)) : ((d[2] >> 16) | (d[3] & 0xffff0000u));
+    const uint32_t r0 = xr(s0, 1), r1 = xr(s1, 1);
+    if (b) {
+      d[0] = (r0 & 0xffffu) | (d[0] & 0xffff0000u);
+      d[1] = (r0 >> 16) | (d[1] & 0xffff0000u);
+      d[2] = (r1 & 0xffffu) | (d[2] & 0xffff0000u);
+      d[3] = (r1 >> 16) | (d[3] & 0xffff0000u);
+    } else {
+      d[0] = (d[0] & 0xffffu) | (r0 << 16);
+      d[1] = (d[1] & 0xffffu) | (r0 & 0xffff0000u);
+      d[2] = (d[2] & 0xffffu) | (r1 << 16);
+      d[3] = (d[3] & 0xffffu) | (r1 & 0xffff0000u);
+    }
+  }
+  return d;
+}
+
+template <typename G, int K, int CG, bool ADJ, typename TS>
+__device__ __forceinline__ void stage_store(const BankParams& p, int64_t oy0, int64_t ox0, int wave, int lane,
+                                            const Raw<TS, G::NT>& st, uint16_t* __restrict__ sl) {
+  const int j = lane & 7;
 #pragma unroll
-    for (int h = 0; h < 4; ++h) {
-      const int c = cg * 8 + 2 * h;
-      const uint32_t lo = (valid && c < p.CI) ? st.get(it, 2 * h) : 0u;
-      const uint32_t hi = (valid && c + 1 < p.CI) ? st.get(it, 2 * h + 1) : 0u;
-      w[h] = lo | (hi << 16);
+  for (int it = 0; it < G::NT; ++it) {
+    int ly, cg, chunk;
+    bool act;
+    unit_pos<G, CG>(it, wave, lane, ly, cg, chunk, act);
+    bool keep = cg * 8 + j < p.CI;  // padded channels are zero
+    if constexpr (ADJ) {
+      const int64_t gy = p.row0 + oy0 - G::R + ly;
+      keep = keep && gy >= 0 && gy < p.H;
     }
-    *reinterpret_cast<uint4*>(sl + (ly * G::LW + lx) * G::PS + cg * 8) = make_uint4(w[0], w[1], w[2], w[3]);
+    u32x4 d = st.pairs(it);
+    if (p.s_vec) {  // chunks outside the row: edge value (clamp) or zero (adjoint)
+      const int64_t gx0 = ox0 - 8 + 8 * chunk;
+      if (gx0 < 0 || gx0 >= p.W) {
+        const uint32_t e = gx0 < 0 ? (d[0] & 0xffffu) : (d[3] >> 16);
+        const uint32_t b = ADJ ? 0u : (e | (e << 16));
+        d = u32x4{b, b, b, b};
+      }
+    }
+    if (!keep) d = u32x4{0u, 0u, 0u, 0u};
+    d = transpose8(d, j);  // channels cg*8 .. cg*8+7 of pixel chunk*8 + j
+    if (act) *reinterpret_cast<u32x4*>(sl + (ly * G::LW + chunk * 8 + j) * G::PS + cg * 8) = d;
   }
 }
 
@@ -292,6 +396,36 @@ __device__ __forceinline__ void store1(void* dst, int64_t o, float v) {
     static_cast<float*>(dst)[o] = v;
 }
 
+// Store one lane's 4 consecutive outputs (pixels ox_l .. ox_l+3 of output
+// channel co, tile row oy): one vector store inside the image, else element
+// stores (adjoint: frame values to the frame buffer, columns outside the
+// frame skipped).
+template <bool ADJ, bool OUT_BF16>
+__device__ __forceinline__ void store_px4(const BankParams& p, int64_t n, int co, int64_t oy, int64_t ox_l,
+                                          const f32x4& v) {
+  if (oy >= p.rows || co >= p.CO) return;
+  const int64_t iy = ADJ ? p.row0 + oy : oy;  // adjoint: image row
+  const bool inside = p.d_vec && (!ADJ || (iy >= 0 && iy < p.H && ox_l >= 0)) && ox_l + 4 <= p.W;
+  if (inside) {
+    store4<OUT_BF16>(p.dst, n * p.d_sn + static_cast<int64_t>(co) * p.d_sc + iy * p.d_sh + ox_l, v);
+    return;
+  }
+#pragma unroll
+  for (int j = 0; j < 4; ++j) {
+    const int64_t ox = ox_l + j;
+    if constexpr (ADJ) {
+      if (ox < -p.fr || ox >= p.W + p.fr) continue;
+      if (iy >= 0 && iy < p.H && ox >= 0 && ox < p.W)
+        store1<false>(p.dst, n * p.d_sn + co * p.d_sc + iy * p.d_sh + ox, v[j]);
+      else
+        p.frame[(n * p.CO + co) * p.frame_plane + frame_index(iy, ox, p.H, p.W, p.fr)] = v[j];
+    } else {
+      if (ox >= p.W) continue;
+      store1<OUT_BF16>(p.dst, n * p.d_sn + co * p.d_sc + iy * p.d_sh + ox, v[j]);
+    }
+  }
+}
+
 // Persistent work-group over (image, output group, 4 x 64-pixel tile).
 // Iteration for tile t:  issue the loads of tile t+1  ->  MFMA over tile t
 // (LDS buffer c)  ->  pack tile t+1 into LDS buffer 1-c  ->  store tile t's
@@ -316,7 +450,7 @@ __global__ __launch_bounds__(kConvThreads) void k_bank_conv(BankParams p) {
   const int l16 = lane % 16, q = lane / 16;
   constexpr int HP = PT / 2;                     // 16-pixel blocks per wave
   const uint16_t* w_lane = wl + l16 * G::WSTR + q * 8;
-  const int b_off = (wrow * G::LW + wcol + l16) * G::PS + (CG >= 4 ? q * 8 : (CG == 2 ? (q & 1) * 8 : 0));
+  const int b_off = (wrow * G::LW + wcol + l16 + G::XOFF) * G::PS + (CG >= 4 ? q * 8 : (CG == 2 ? (q & 1) * 8 : 0));
   const bool hsel = (q >> 1) != 0;
 
   const int64_t per_group = static_cast<int64_t>(p.tiles_x) * p.tiles_y;
@@ -338,7 +472,7 @@ __global__ __launch_bounds__(kConvThreads) void k_bank_conv(BankParams p) {
   int og;
   decode(t, n, og, oy0, ox0);
   Raw<TS, G::NT> st;
-  stage_load<G, K, CG, TS>(p, n, oy0, ox0, wave, lane, st);
+  stage_load<G, K, CG, ADJ, TS>(p, n, oy0, ox0, wave, lane, st);
   load_weights<G, K, OT, CG, ADJ>(p, og, tid, wl);
   stage_store<G, K, CG, ADJ, TS>(p, oy0, ox0, wave, lane, st, sl0);
   __syncthreads();
@@ -351,7 +485,7 @@ __global__ __launch_bounds__(kConvThreads) void k_bank_conv(BankParams p) {
     int64_t n2, oy2, ox2;
     int og2;
     decode(more ? t_next : t, n2, og2, oy2, ox2);
-    stage_load<G, K, CG, TS>(p, n2, oy2, ox2, wave, lane, st);
+    stage_load<G, K, CG, ADJ, TS>(p, n2, oy2, ox2, wave, lane, st);
     __builtin_amdgcn_sched_barrier(0);  // keep every prefetch load ahead of the MFMA loop
 
     const uint16_t* sl = sl0 + cur * G::S_ELEMS;
@@ -397,45 +531,12 @@ __global__ __launch_bounds__(kConvThreads) void k_bank_conv(BankParams p) {
 
     // acc[a][b][j] = output channel og*OT*16 + 16a + l16, pixel
     // ox0 + wcol + 16b + 4q + j of tile row wrow
-    const int64_t oy = oy0 + wrow;
-    if (oy < p.rows) {
-      const int64_t iy = ADJ ? p.row0 + oy : oy;  // adjoint: image row
-      const int64_t ox_l = ox0 + wcol + 4 * q;
-      const int co_l = og * OT * 16 + l16;
-      const bool inside = p.d_vec && (!ADJ || (iy >= 0 && iy < p.H && ox0 + wcol >= 0)) &&
-                          ox0 + wcol + 16 * HP <= p.W;
-      if (inside) {
-        const int64_t base = n * p.d_sn + static_cast<int64_t>(co_l) * p.d_sc + iy * p.d_sh + ox_l;
 #pragma unroll
-        for (int a = 0; a < OT; ++a) {
-          if (co_l + a * 16 >= p.CO) continue;
+    for (int a = 0; a < OT; ++a)
 #pragma unroll
-          for (int b = 0; b < HP; ++b) store4<OUT_BF16>(p.dst, base + a * 16 * p.d_sc + 16 * b, acc[a][b]);
-        }
-      } else {
-#pragma unroll
-        for (int a = 0; a < OT; ++a) {
-          const int co = co_l + a * 16;
-          if (co >= p.CO) continue;
-#pragma unroll
-          for (int b = 0; b < HP; ++b)
-#pragma unroll
-            for (int j = 0; j < 4; ++j) {
-              const int64_t ox = ox_l + 16 * b + j;
-              if constexpr (ADJ) {
-                if (ox < -p.fr || ox >= p.W + p.fr) continue;
-                if (iy >= 0 && iy < p.H && ox >= 0 && ox < p.W)
-                  store1<false>(p.dst, n * p.d_sn + co * p.d_sc + iy * p.d_sh + ox, acc[a][b][j]);
-                else
-                  p.frame[(n * p.CO + co) * p.frame_plane + frame_index(iy, ox, p.H, p.W, p.fr)] = acc[a][b][j];
-              } else {
-                if (ox >= p.W) continue;
-                store1<OUT_BF16>(p.dst, n * p.d_sn + co * p.d_sc + iy * p.d_sh + ox, acc[a][b][j]);
-              }
-            }
-        }
-      }
-    }
+      for (int b = 0; b < HP; ++b)
+        store_px4<ADJ, OUT_BF16>(p, n, og * OT * 16 + l16 + 16 * a, oy0 + wrow, ox0 + wcol + 16 * b + 4 * q,
+                                 acc[a][b]);
     __syncthreads();  // tile t+1 staged; everyone done with buffer cur
     if (!more) break;
     t = t_next;
@@ -790,6 +891,7 @@ f2d_status bank_forward_bf16(const Problem& pr, const f2d_tensor* outs, hipStrea
   p.s_sn = im.stride_n;
   p.s_sc = im.stride_c;
   p.s_sh = im.stride_h;
+  p.s_vec = row_aligned(im, 16) && im.w % 8 == 0 ? 1 : 0;
   p.dst = out.data;
   p.d_sn = out.stride_n;
   p.d_sc = out.stride_c;
@@ -846,6 +948,7 @@ f2d_status bank_backward_bf16(const Problem& pr, const f2d_tensor& gout, const f
     p.s_sn = gout.stride_n;
     p.s_sc = gout.stride_c;
     p.s_sh = gout.stride_h;
+    p.s_vec = row_aligned(gout, 16) && im.w % 8 == 0 ? 1 : 0;
     p.dst = grad_input->data;
     p.d_sn = grad_input->stride_n;
     p.d_sc = grad_input->stride_c;
@@ -858,7 +961,7 @@ f2d_status bank_backward_bf16(const Problem& pr, const f2d_tensor& gout, const f
     p.row0 = -r;  // the image and its r-wide frame
     p.rows = im.h + 2 * r;
     // tile columns start 4-aligned left of the frame (columns < -r are skipped)
-    p.col0 = -((r + 3) / 4) * 4;
+    p.col0 = -8;  // 8-aligned staging chunks; columns < -r are skipped
     p.fr = static_cast<int32_t>(r);
     p.frame = static_cast<float*>(ws);
     p.frame_plane = frame_plane_size(im.h, im.w, r);
