@@ -105,6 +105,26 @@ def test_forward_wide_input_bank(gpu_lib, k):
     assert_same(host(y), oracle.forward(xv, fv, "bank"))
 
 
+@pytest.mark.parametrize("k", [3, 5])
+def test_strided_views_take_the_element_staging(gpu_lib, k):
+    """Image and upstream gradient as views with a row pitch that is not a
+    multiple of 8 elements (and W not a multiple of 8): the staging falls back
+    to clamped element loads; results stay bit-exact."""
+    r = wl.rng(35, k)
+    xb = r.integers(-8, 9, (1, 16, 30, 83)).astype(np.float32)
+    gb = r.integers(-8, 9, (1, 64, 30, 83)).astype(np.float32)
+    f = r.integers(-8, 9, (64, 16, k, k)).astype(np.float32)
+    xd_full, _ = bf(xb)
+    gd_full, _ = bf(gb)
+    xd, gd = xd_full[:, :, 2:28, 3:80], gd_full[:, :, 2:28, 3:80]  # 26 x 77 views, pitch 83
+    x, g = xb[:, :, 2:28, 3:80], gb[:, :, 2:28, 3:80]
+    fd, fv = bf(f)
+    assert_same(host(gpu_lib.forward(xd, fd, mode="bank")), oracle.forward(x, fv, "bank"))
+    gi, gf = gpu_lib.backward(xd, fd, gd, mode="bank")
+    assert_same(host(gi), oracle.grad_input(g, fv, x.shape, "bank"))
+    assert_same(host(gf), oracle.grad_filter(x, g, f.shape, "bank"))
+
+
 def test_bf16_bank_rows_band(gpu_lib):
     k = 5
     r = wl.rng(32)
