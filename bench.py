@@ -317,7 +317,7 @@ def main():
     ap.add_argument("--warmup", type=int, default=20)
     ap.add_argument("--no-suite", action="store_true", help="headline workload only")
     ap.add_argument("--suite-reps", type=int, default=10)
-    ap.add_argument("--cpu-seconds", type=float, default=10.0, help="oracle sample budget")
+    ap.add_argument("--cpu-seconds", type=float, default=15.0, help="oracle sample budget")
     ap.add_argument("--no-cpu", action="store_true", help="skip the oracle baseline")
     ap.add_argument("--profile", action="store_true",
                     help="counter-profiling run: headline kernel --steps times + a 1 GiB copy")
