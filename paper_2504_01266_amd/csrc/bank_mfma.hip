@@ -1,27 +1,29 @@
 // BF16 filter banks on the gfx950 matrix cores (FP32 accumulation).
 //
 // A bank Y[n][o] = sum_i corr(X[n][i], W[o][i]) is an implicit GEMM: for
-// every output pixel p, Y[o][p] = sum_k A[o][k] * B[k][p] with the
-// contraction index k = (tap (u,v), input channel i), A = the weights and
-// B = the K*K-neighbourhood of p (never materialised: it is read from an LDS
-// tile with its clamped halo).  k is ordered tap-major, channel-minor, so one
-// 8-element MFMA operand slice is 8 consecutive channels of one pixel, i.e.
-// 16 contiguous bytes of the channels-last LDS tile.
+// every output pixel p and output channel o, Y[p][o] = sum_k A[p][k] * B[k][o]
+// with the contraction index k = (tap (u,v), input channel i), A = the K*K
+// neighbourhood of p (never materialised: it is read from an LDS tile with
+// its clamped halo) and B = the weights.  k is ordered tap-major,
+// channel-minor, so one 8-element MFMA operand slice is 8 consecutive
+// channels of one pixel, i.e. 16 contiguous bytes of the channels-last tile.
 //
 //  k_bank_conv   v_mfma_f32_16x16x32_bf16.  A persistent work-group keeps
-//                the whole weight matrix (all taps x channels of OT*16 output
-//                channels) in LDS and loops over 4 x (16*PT)-pixel tiles; each
-//                wave owns one tile row and OT x PT 16x16 accumulator blocks.
-//                Forward: clamp-to-edge borders.  Adjoint in the image
-//                (dgrad): zero borders and the transposed, flipped weights,
-//                evaluated on the image plus an r-wide frame whose values are
-//                then folded onto the edge pixels (the exact clamp adjoint).
-//                Upstream gradients given in FP32 are rounded to BF16
-//                (nearest even) while they are staged.
+//                the weights of its current output group (all taps x channels
+//                of OT*16 output channels) in LDS and walks 4 x (16*PT)-pixel
+//                tiles; the next tile's global loads are in flight during the
+//                MFMA loop and land in the second LDS tile buffer after it.
+//                Each wave owns one tile row, half of its pixels, and
+//                OT x PT/2 16x16 accumulator blocks.  Forward: clamp-to-edge borders.
+//                Adjoint in the image (dgrad): zero borders and the
+//                transposed, flipped weights, evaluated on the image plus an
+//                r-wide frame whose values are then folded onto the edge
+//                pixels (the exact clamp adjoint).  Upstream gradients given
+//                in FP32 are rounded to BF16 (nearest even) while staged.
 //  k_bank_wgrad  W-bar[o][i][u][v] = sum_p G[o][p] * X[i][shift_uv(p)]: for
 //                every tap a 16(o) x 16(i) block contracted over 32-pixel
-//                steps; the shifted X operand is built from three aligned
-//                16-byte LDS reads per row and byte-aligned funnel shifts.
+//                steps; each staged X row is read once as a window and the
+//                K horizontal shifts are built with 16-bit funnel shifts.
 //                Per-unit partials go to the workspace and are reduced in a
 //                fixed order.
 #include <hip/hip_bf16.h>
