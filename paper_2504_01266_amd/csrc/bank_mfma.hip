@@ -31,6 +31,7 @@
 
 #include <cstring>
 #include <mutex>
+#include <type_traits>
 
 #include "f2d_host.hpp"
 #include "f2d_internal.hpp"
@@ -46,9 +47,16 @@ typedef uint16_t u16x2 __attribute__((ext_vector_type(2)));
 
 constexpr int kThreads = 256;      // wgrad work-group
 constexpr int kWaves = 4;
-constexpr int kConvThreads = 512;  // conv work-group: 8 waves, two per tile row
-constexpr int kConvWaves = 8;
 constexpr int kTH = 4;             // conv tile rows
+
+// f(integral_constant<int, 0>) ... f(integral_constant<int, N-1>), in order
+template <int N, int I = 0, typename F>
+__device__ __forceinline__ void static_for(F&& f) {
+  if constexpr (I < N) {
+    f(std::integral_constant<int, I>{});
+    static_for<N, I + 1>(f);
+  }
+}
 
 struct BankParams {
   const void* src;  // source planes: X (bf16) or, for the adjoint, G-bar (bf16 or f32)
@@ -61,6 +69,7 @@ struct BankParams {
   int32_t fo, fi;  // forward weight extents
   int32_t tiles_x, tiles_y, o_groups;
   int64_t n_tiles;  // N * o_groups * tiles_y * tiles_x
+  int64_t n_img, cols;  // images, and output columns from col0 to cover (tiles_x from the tile width)
   // adjoint: output rows start at row0 = -r and columns at col0 <= -r (4-aligned); values
   // on the r-wide frame go to `frame` (frame_plane floats per output plane)
   int64_t col0;
@@ -71,12 +80,15 @@ struct BankParams {
   int32_t s_vec;  // source rows and planes 16-byte aligned and W % 8 == 0 (vector staging)
 };
 
+// FP32 -> BF16, round to nearest even (NaN stays NaN): the gfx950 packed
+// conversion instruction, one per pair of values.
+typedef __bf16 bf16x2 __attribute__((ext_vector_type(2)));
+typedef float f32x2 __attribute__((ext_vector_type(2)));
+__device__ __forceinline__ uint32_t pack_bf16x2(float lo, float hi) {
+  return __builtin_bit_cast(uint32_t, __builtin_convertvector(f32x2{lo, hi}, bf16x2));
+}
 __device__ __forceinline__ uint16_t f32_to_bf16_bits(float f) {
-  // round to nearest even (NaN kept quiet)
-  uint32_t u = __float_as_uint(f);
-  if ((u & 0x7f800000u) == 0x7f800000u && (u & 0x7fffffu)) return static_cast<uint16_t>((u >> 16) | 0x40);
-  u += 0x7fffu + ((u >> 16) & 1u);
-  return static_cast<uint16_t>(u >> 16);
+  return __builtin_bit_cast(uint16_t, static_cast<__bf16>(f));
 }
 
 template <typename TS>
@@ -90,14 +102,29 @@ __device__ __forceinline__ uint16_t load_bits<float>(const float* p) {
   return f32_to_bf16_bits(*p);
 }
 
-template <int K, int OT, int PT, int CG>
+// Conv work-group of NW waves (4, 8 or 16) over a kTH x TW tile: NW/kTH
+// waves per tile row, each with HP 16-pixel blocks.  Groups of eight or more
+// waves may use all of LDS; four-wave groups stay within half of it so that
+// two fit on a CU.
+template <int K, int OT, int PT, int CG, int NW>
 struct ConvGeom {
+  static constexpr int THREADS = 64 * NW;
+  static constexpr int WPR = NW / kTH;               // waves per tile row
+  static constexpr int HP = PT / WPR;                // 16-pixel blocks per wave
+  static constexpr int LDS_CAP = NW >= 8 ? 160 * 1024 : 80 * 1024;
   static constexpr int R = (K - 1) / 2;
   static constexpr int CI8 = CG * 8;         // staged channels (padded)
   static constexpr int KG = K * K * CG;      // 8-wide k-groups
   static constexpr int STEPS = (KG + 3) / 4; // 32-wide MFMA steps
   static constexpr int KP = STEPS * 32;
-  static constexpr int WSTR = KP + 8;        // weight row stride (elements), staggers banks
+  // LDS strides.  A ds_read_b128 is served in two halves of 32 lanes, each
+  // over a 512-byte bank window: the 32 accesses of a half must fall in 32
+  // distinct 16-byte slots mod 512 bytes.  MFMA operand reads put 16 rows
+  // (weight rows, or pixels) at a fixed stride and two 16-byte k-groups per
+  // half; both are conflict-free when the row stride is an odd multiple of
+  // 32 bytes (the 16 rows then take every even slot, the second k-group
+  // every odd one).  KP*2 bytes is a multiple of 64, so 32 bytes are added.
+  static constexpr int WSTR = KP + 16;       // weight row stride (elements)
   static constexpr int TW = 16 * PT;
   static constexpr int LH = kTH + K - 1;
   // staged columns x0-8 .. x0+TW+7: 16-byte aligned 8-column chunks (R <= 8);
@@ -105,18 +132,24 @@ struct ConvGeom {
   static constexpr int LW = TW + 16;
   static constexpr int XOFF = 8 - R;
   static constexpr int CHUNKS = LW / 8;
-  // channels-last pixel stride padded by 16 bytes: 16 lanes reading 16 bytes
-  // at consecutive pixels then cover all 64 LDS banks exactly once
-  static constexpr int PS = CI8 + 8;
-  static constexpr int S_ELEMS = LH * LW * PS;      // one source tile (16-byte multiple)
+  // channels-last pixel stride (elements): an odd multiple of 32 bytes where
+  // that keeps two source buffers in LDS (see WSTR; with CG = 1 the four
+  // quarters read four taps and no stride avoids every conflict), else the
+  // smallest 16-byte-padded stride
+  static constexpr int PS_CF = CG == 2 ? 16 : (CG == 1 ? 16 : CI8 + 16);
+  static constexpr int PS_MIN = CI8 + 8;
   static constexpr int W_ELEMS = OT * 16 * WSTR;
-  // weights + two source tiles when they fit in LDS (160 KiB), else one
-  static constexpr int NBUF = (W_ELEMS + 2 * S_ELEMS) * 2 <= 160 * 1024 ? 2 : 1;
+  static constexpr bool fits2(int ps) { return (W_ELEMS + 2 * LH * LW * ps) * 2 <= LDS_CAP; }
+  static constexpr int PS = fits2(PS_CF) || !fits2(PS_MIN) ? PS_CF : PS_MIN;
+  static constexpr int S_ELEMS = LH * LW * PS;      // one source tile (16-byte multiple)
+  // weights + two source tiles when they fit in the LDS share, else one
+  static constexpr int NBUF = fits2(PS) ? 2 : 1;
   static constexpr int LDS_ELEMS = W_ELEMS + NBUF * S_ELEMS;
   // staging units (row, channel group, 8-column chunk), 8 per wave instruction
   static constexpr int UNITS = LH * CG * CHUNKS;
-  static constexpr int NT = (UNITS + 8 * kConvWaves - 1) / (8 * kConvWaves);  // per wave
+  static constexpr int NT = (UNITS + 8 * NW - 1) / (8 * NW);  // per wave
   static_assert(R <= 8, "K <= 17");
+  static_assert(NW % kTH == 0 && PT % WPR == 0, "tile split");
 };
 
 // Staging of the source tile, channels-last.  A unit = (row ly, channel
@@ -129,7 +162,7 @@ struct ConvGeom {
 // applied to the values.
 template <typename G, int CG>
 __device__ __forceinline__ void unit_pos(int it, int wave, int lane, int& ly, int& cg, int& chunk, bool& act) {
-  const int u = (it * kConvWaves + wave) * 8 + (lane >> 3);
+  const int u = (it * (G::THREADS / 64) + wave) * 8 + (lane >> 3);
   act = u < G::UNITS;
   const int uu = act ? u : 0;
   chunk = uu % G::CHUNKS;
@@ -156,8 +189,7 @@ struct Raw<float, NT> {
     u32x4 r;
 #pragma unroll
     for (int d = 0; d < 4; ++d)
-      r[d] = static_cast<uint32_t>(f32_to_bf16_bits(v[it][2 * d])) |
-             (static_cast<uint32_t>(f32_to_bf16_bits(v[it][2 * d + 1])) << 16);
+      r[d] = pack_bf16x2(v[it][2 * d], v[it][2 * d + 1]);
     return r;
   }
 };
@@ -301,12 +333,12 @@ __device__ __forceinline__ u32x4 transpose8(u32x4 d, int j) {
   return d;
 }
 
+// Transpose and LDS write of staging unit `it` of this wave.
 template <typename G, int K, int CG, bool ADJ, typename TS>
-__device__ __forceinline__ void stage_store(const BankParams& p, int64_t oy0, int64_t ox0, int wave, int lane,
-                                            const Raw<TS, G::NT>& st, uint16_t* __restrict__ sl) {
+__device__ __forceinline__ void stage_store_unit(const BankParams& p, int64_t oy0, int64_t ox0, int wave, int lane,
+                                                 const Raw<TS, G::NT>& st, uint16_t* __restrict__ sl, int it) {
   const int j = lane & 7;
-#pragma unroll
-  for (int it = 0; it < G::NT; ++it) {
+  {
     int ly, cg, chunk;
     bool act;
     unit_pos<G, CG>(it, wave, lane, ly, cg, chunk, act);
@@ -328,6 +360,13 @@ __device__ __forceinline__ void stage_store(const BankParams& p, int64_t oy0, in
     d = transpose8(d, j);  // channels cg*8 .. cg*8+7 of pixel chunk*8 + j
     if (act) *reinterpret_cast<u32x4*>(sl + (ly * G::LW + chunk * 8 + j) * G::PS + cg * 8) = d;
   }
+}
+
+template <typename G, int K, int CG, bool ADJ, typename TS>
+__device__ __forceinline__ void stage_store(const BankParams& p, int64_t oy0, int64_t ox0, int wave, int lane,
+                                            const Raw<TS, G::NT>& st, uint16_t* __restrict__ sl) {
+#pragma unroll
+  for (int it = 0; it < G::NT; ++it) stage_store_unit<G, K, CG, ADJ, TS>(p, oy0, ox0, wave, lane, st, sl, it);
 }
 
 // LDS offset (elements) of tap t in the channels-last tile, relative to the
@@ -364,7 +403,7 @@ __device__ __forceinline__ int b_step_offset(int s, bool hsel, int q) {
 // (zero for padded k-groups, channels and outputs).
 template <typename G, int K, int OT, int CG, bool ADJ>
 __device__ __forceinline__ void load_weights(const BankParams& p, int og, int tid, uint16_t* __restrict__ wl) {
-  for (int idx = tid; idx < OT * 16 * G::KP; idx += kConvThreads) {
+  for (int idx = tid; idx < OT * 16 * G::KP; idx += G::THREADS) {
     const int col = idx / G::KP, k = idx - col * G::KP;
     const int co = og * OT * 16 + col;
     const int gi = k / 8, ci = (gi % CG) * 8 + k % 8, uv = gi / CG;
@@ -383,8 +422,8 @@ __device__ __forceinline__ void load_weights(const BankParams& p, int og, int ti
 template <bool OUT_BF16>
 __device__ __forceinline__ void store4(void* dst, int64_t o, const f32x4& v) {
   if constexpr (OUT_BF16) {
-    const uint32_t lo = f32_to_bf16_bits(v[0]) | (static_cast<uint32_t>(f32_to_bf16_bits(v[1])) << 16);
-    const uint32_t hi = f32_to_bf16_bits(v[2]) | (static_cast<uint32_t>(f32_to_bf16_bits(v[3])) << 16);
+    const uint32_t lo = pack_bf16x2(v[0], v[1]);
+    const uint32_t hi = pack_bf16x2(v[2], v[3]);
     *reinterpret_cast<uint2*>(static_cast<uint16_t*>(dst) + o) = make_uint2(lo, hi);
   } else {
     *reinterpret_cast<float4*>(static_cast<float*>(dst) + o) = make_float4(v[0], v[1], v[2], v[3]);
@@ -428,29 +467,37 @@ __device__ __forceinline__ void store_px4(const BankParams& p, int64_t n, int co
   }
 }
 
-// Persistent work-group over (image, output group, 4 x 64-pixel tile).
-// Iteration for tile t:  issue the loads of tile t+1  ->  MFMA over tile t
-// (LDS buffer c)  ->  pack tile t+1 into LDS buffer 1-c  ->  store tile t's
-// outputs  ->  one barrier.  (With a single source buffer, when two do not
-// fit in LDS, a barrier also precedes the packing.)  Stores of tile t drain while tile t+1 computes;
-// the wait for tile t+2's loads covers them only after that MFMA phase.
+// Persistent work-group over (image, output group, kTH x TW tile).  Each wave
+// computes OT*16 output channels x HP*16 pixels of one tile row in NP passes
+// of OTP*16 channels (one full sweep over k per pass, 32 accumulators).
+//
+//  * the loads of tile t+1 are issued when tile t starts; with two source
+//    buffers, tile t+1 is packed into the idle buffer unit by unit between
+//    the MFMA groups of tile t's last sweep, so its VALU and LDS work runs
+//    beside the matrix cores of the other waves;
+//  * each pass stores its results right after its sweep;
+//  * one barrier per tile (plus one before repacking when a single source
+//    buffer fits, or before reloading the weights of a new output group).
 //
 // MFMA operands: A = 16 pixels x 32 k (the source tile), B = 32 k x 16 output
 // channels (the weights), so D[pixel 4q + j][channel l16]: each lane holds 4
 // consecutive pixels of one output channel and writes them with one store.
-template <int K, int OT, int PT, int CG, bool ADJ, typename TS, bool OUT_BF16>
-__global__ __launch_bounds__(kConvThreads) void k_bank_conv(BankParams p) {
-  using G = ConvGeom<K, OT, PT, CG>;
+template <int K, int OT, int PT, int CG, int NW, bool ADJ, typename TS, bool OUT_BF16>
+__global__ __launch_bounds__(64 * NW) void k_bank_conv(BankParams p) {
+  using G = ConvGeom<K, OT, PT, CG, NW>;
+  constexpr int HP = G::HP;
+  constexpr int OTP = OT < 2 ? OT : 2;  // 16-channel blocks per pass
+  constexpr int NP = OT / OTP;
+  static_assert(OT % OTP == 0, "passes");
   extern __shared__ uint4 smem4[];
   uint16_t* wl = reinterpret_cast<uint16_t*>(smem4);
   uint16_t* sl0 = wl + G::W_ELEMS;
   const int tid = threadIdx.x;
   const int lane = tid % 64;
   const int wave = __builtin_amdgcn_readfirstlane(tid / 64);
-  const int wrow = wave % kTH;                   // this wave's tile row
-  const int wcol = (wave / kTH) * (G::TW / 2);   // and its half of the columns
+  const int wrow = wave % kTH;                      // this wave's tile row
+  const int wcol = (wave / kTH) * (G::TW / G::WPR); // and its share of the columns
   const int l16 = lane % 16, q = lane / 16;
-  constexpr int HP = PT / 2;                     // 16-pixel blocks per wave
   const uint16_t* w_lane = wl + l16 * G::WSTR + q * 8;
   const int b_off = (wrow * G::LW + wcol + l16 + G::XOFF) * G::PS + (CG >= 4 ? q * 8 : (CG == 2 ? (q & 1) * 8 : 0));
   const bool hsel = (q >> 1) != 0;
@@ -478,6 +525,7 @@ __global__ __launch_bounds__(kConvThreads) void k_bank_conv(BankParams p) {
   load_weights<G, K, OT, CG, ADJ>(p, og, tid, wl);
   stage_store<G, K, CG, ADJ, TS>(p, oy0, ox0, wave, lane, st, sl0);
   __syncthreads();
+
   int cur = 0;
   while (true) {
     const int64_t t_next = t + gridDim.x;
@@ -490,55 +538,77 @@ __global__ __launch_bounds__(kConvThreads) void k_bank_conv(BankParams p) {
     stage_load<G, K, CG, ADJ, TS>(p, n2, oy2, ox2, wave, lane, st);
     __builtin_amdgcn_sched_barrier(0);  // keep every prefetch load ahead of the MFMA loop
 
-    const uint16_t* sl = sl0 + cur * G::S_ELEMS;
-    const uint16_t* b_lane = sl + b_off;
-    f32x4 acc[OT][HP];
+    const uint16_t* b_lane = sl0 + cur * G::S_ELEMS + b_off;
+    uint16_t* sl_next = sl0 + (cur ^ 1) * G::S_ELEMS;
+    static_for<NP>([&](auto pass) {
+      constexpr int P = decltype(pass)::value;
+      const uint16_t* w_pass = w_lane + P * OTP * 16 * G::WSTR;
+      f32x4 acc[OTP][HP];
 #pragma unroll
-    for (int a = 0; a < OT; ++a)
+      for (int a = 0; a < OTP; ++a)
 #pragma unroll
-      for (int b = 0; b < HP; ++b) acc[a][b] = f32x4{0.f, 0.f, 0.f, 0.f};
-    // Operand addresses: a per-lane base plus a per-step constant, so that in
-    // the unrolled step loop every LDS read carries its step offset as an
-    // immediate.  Lane quarter q holds k-group gi = 4s + q of step s.
+        for (int b = 0; b < HP; ++b) acc[a][b] = f32x4{0.f, 0.f, 0.f, 0.f};
+      // Operand addresses: a per-lane base plus a per-step constant, so that
+      // in the unrolled step loop every LDS read carries its step offset as
+      // an immediate.  Lane quarter q holds k-group gi = 4s + q of step s.
+      // The operands of step s+1 are read while the MFMAs of step s run (two
+      // register sets); the scheduling fences keep the compiler from sinking
+      // the reads back next to their uses.
+      bf16x8 wf[2][OTP], xf[2][HP];
+      auto fetch = [&](auto step, int set) {
+        constexpr int s = decltype(step)::value;
 #pragma unroll
-    for (int s = 0; s < G::STEPS; ++s) {
-      bf16x8 wf[OT], xf[HP];
+        for (int a = 0; a < OTP; ++a)
+          wf[set][a] = *reinterpret_cast<const bf16x8*>(w_pass + a * 16 * G::WSTR + 32 * s);
+        // b_step_offset clamps taps past K*K to tap 0, so every read is of
+        // staged pixels; quarters holding a padded k-group (past KG, only in
+        // the last step) zero their operand in registers
+        const uint16_t* bp = b_lane + b_step_offset<G, K, CG>(s, hsel, q);
+        const bool pad = 4 * s + 3 >= G::KG && 4 * s + q >= G::KG;
 #pragma unroll
-      for (int a = 0; a < OT; ++a) wf[a] = *reinterpret_cast<const bf16x8*>(w_lane + a * 16 * G::WSTR + 32 * s);
-      // b_step_offset clamps taps past K*K to tap 0, so every read is of
-      // staged pixels; quarters holding a padded k-group (past KG, only in
-      // the last step) zero their operand in registers
-      const uint16_t* bp = b_lane + b_step_offset<G, K, CG>(s, hsel, q);
-      const bool pad = 4 * s + 3 >= G::KG && 4 * s + q >= G::KG;
+        for (int b = 0; b < HP; ++b) {
+          xf[set][b] = *reinterpret_cast<const bf16x8*>(bp + b * 16 * G::PS);
+          if (pad) xf[set][b] = bf16x8{};
+        }
+      };
+      // in the last pass, with two source buffers, staging unit S0+u goes
+      // after step S0+u (the last step also takes any left over)
+      constexpr int S0 = G::STEPS > G::NT ? G::STEPS - G::NT : 0;
+      fetch(std::integral_constant<int, 0>{}, 0);
+      static_for<G::STEPS>([&](auto step) {
+        constexpr int s = decltype(step)::value;
+        if constexpr (s + 1 < G::STEPS) fetch(std::integral_constant<int, s + 1>{}, (s + 1) & 1);
+        __builtin_amdgcn_sched_barrier(0);
 #pragma unroll
-      for (int b = 0; b < HP; ++b) {
-        xf[b] = *reinterpret_cast<const bf16x8*>(bp + b * 16 * G::PS);
-        if (pad) xf[b] = bf16x8{};
-      }
+        for (int a = 0; a < OTP; ++a)
 #pragma unroll
-      for (int a = 0; a < OT; ++a)
+          for (int b = 0; b < HP; ++b)
+            acc[a][b] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(xf[s & 1][b], wf[s & 1][a], acc[a][b], 0, 0, 0);
+        if constexpr (P == NP - 1 && G::NBUF == 2) {
+          constexpr int u0 = s - S0, u1 = s == G::STEPS - 1 ? G::NT : s - S0 + 1;
+#pragma unroll
+          for (int u = u0 < 0 ? 0 : u0; u < u1; ++u)
+            stage_store_unit<G, K, CG, ADJ, TS>(p, oy2, ox2, wave, lane, st, sl_next, u);
+        }
+        __builtin_amdgcn_sched_barrier(0);
+      });
+      // acc[a][b][j] = output channel (og*NP + P)*OTP*16 + 16a + l16, pixel
+      // ox0 + wcol + 16b + 4q + j of tile row wrow
+      const int co0 = (og * NP + P) * OTP * 16 + l16;
+#pragma unroll
+      for (int a = 0; a < OTP; ++a)
 #pragma unroll
         for (int b = 0; b < HP; ++b)
-          acc[a][b] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(xf[b], wf[a], acc[a][b], 0, 0, 0);
-    }
-    __builtin_amdgcn_sched_barrier(0);
+          store_px4<ADJ, OUT_BF16>(p, n, co0 + 16 * a, oy0 + wrow, ox0 + wcol + 16 * b + 4 * q, acc[a][b]);
+    });
 
     if (more) {
       // a new output group, or a single source buffer: wait until every wave
       // is done reading (uniform branch)
       if (og2 != og || G::NBUF == 1) __syncthreads();
       if (og2 != og) load_weights<G, K, OT, CG, ADJ>(p, og2, tid, wl);
-      stage_store<G, K, CG, ADJ, TS>(p, oy2, ox2, wave, lane, st, sl0 + (G::NBUF == 2 ? cur ^ 1 : 0) * G::S_ELEMS);
+      if constexpr (G::NBUF == 1) stage_store<G, K, CG, ADJ, TS>(p, oy2, ox2, wave, lane, st, sl0);
     }
-
-    // acc[a][b][j] = output channel og*OT*16 + 16a + l16, pixel
-    // ox0 + wcol + 16b + 4q + j of tile row wrow
-#pragma unroll
-    for (int a = 0; a < OT; ++a)
-#pragma unroll
-      for (int b = 0; b < HP; ++b)
-        store_px4<ADJ, OUT_BF16>(p, n, og * OT * 16 + l16 + 16 * a, oy0 + wrow, ox0 + wcol + 16 * b + 4 * q,
-                                 acc[a][b]);
     __syncthreads();  // tile t+1 staged; everyone done with buffer cur
     if (!more) break;
     t = t_next;
@@ -611,8 +681,7 @@ __device__ __forceinline__ bf16x8 g_fragment(const float* src) {
   u32x4 r;
 #pragma unroll
   for (int d = 0; d < 4; ++d)
-    r[d] = static_cast<uint32_t>(f32_to_bf16_bits(f[2 * d])) |
-           (static_cast<uint32_t>(f32_to_bf16_bits(f[2 * d + 1])) << 16);
+    r[d] = pack_bf16x2(f[2 * d], f[2 * d + 1]);
   return __builtin_bit_cast(bf16x8, r);
 }
 
@@ -785,9 +854,12 @@ __global__ __launch_bounds__(kThreads) __attribute__((amdgpu_waves_per_eu(2))) v
 
 // ------------------------------------------------------------- dispatch --
 
-template <int K, int OT, int PT, int CG, bool ADJ, typename TS, bool OB>
-hipError_t conv_go(const BankParams& p, hipStream_t s) {
-  using G = ConvGeom<K, OT, PT, CG>;
+template <int K, int OT, int PT, int CG, int NW, bool ADJ, typename TS, bool OB>
+hipError_t conv_go(const BankParams& pin, hipStream_t s) {
+  using G = ConvGeom<K, OT, PT, CG, NW>;
+  BankParams p = pin;
+  p.tiles_x = static_cast<int32_t>((p.cols + G::TW - 1) / G::TW);
+  p.n_tiles = p.n_img * p.o_groups * static_cast<int64_t>(p.tiles_x) * p.tiles_y;
   const size_t lds = static_cast<size_t>(G::LDS_ELEMS) * 2;
   if (lds > 160 * 1024) return hipErrorInvalidValue;
   static std::mutex mu;
@@ -799,12 +871,12 @@ hipError_t conv_go(const BankParams& p, hipStream_t s) {
   {
     std::lock_guard<std::mutex> lk(mu);
     if (dev_cached != dev) {
-      auto kern = k_bank_conv<K, OT, PT, CG, ADJ, TS, OB>;
+      auto kern = k_bank_conv<K, OT, PT, CG, NW, ADJ, TS, OB>;
       e = hipFuncSetAttribute(reinterpret_cast<const void*>(kern), hipFuncAttributeMaxDynamicSharedMemorySize,
                               static_cast<int>(lds));
       if (e != hipSuccess) return e;
       int per_cu = 0, cus = 0;
-      e = hipOccupancyMaxActiveBlocksPerMultiprocessor(&per_cu, kern, kConvThreads, lds);
+      e = hipOccupancyMaxActiveBlocksPerMultiprocessor(&per_cu, kern, G::THREADS, lds);
       if (e != hipSuccess) return e;
       e = hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, dev);
       if (e != hipSuccess) return e;
@@ -815,32 +887,34 @@ hipError_t conv_go(const BankParams& p, hipStream_t s) {
   }
   const int64_t g = p.n_tiles < grid ? p.n_tiles : grid;
   if (g <= 0) return hipSuccess;
-  hipLaunchKernelGGL((k_bank_conv<K, OT, PT, CG, ADJ, TS, OB>), dim3(static_cast<uint32_t>(g)),
-                     dim3(kConvThreads), lds, s, p);
+  hipLaunchKernelGGL((k_bank_conv<K, OT, PT, CG, NW, ADJ, TS, OB>), dim3(static_cast<uint32_t>(g)),
+                     dim3(G::THREADS), lds, s, p);
   return hipGetLastError();
 }
 
 template <int K, bool ADJ, typename TS, bool OB>
 hipError_t conv_by_shape(const BankParams& p, int ot, int cg, hipStream_t s) {
-  // instantiated (OT, CG) pairs, PT = 4 (64-pixel tile rows); the adjoint's
-  // outputs are the forward's input channels (<= 16, one tile)
+  // instantiated (OT, CG) pairs, eight waves; 64-pixel tile rows (PT = 4),
+  // 128 for 64 outputs from 9..16 inputs, where two source tiles of that
+  // width still fit beside the weights; the adjoint's outputs are the
+  // forward's input channels (<= 16, one tile)
   if constexpr (!ADJ) {
-    if (ot == 4 && cg == 2) return conv_go<K, 4, 4, 2, ADJ, TS, OB>(p, s);
-    if (ot == 4 && cg == 1) return conv_go<K, 4, 4, 1, ADJ, TS, OB>(p, s);
-    if (ot == 4 && cg == 4) return conv_go<K, 4, 4, 4, ADJ, TS, OB>(p, s);
-    if (ot == 2 && cg == 1) return conv_go<K, 2, 4, 1, ADJ, TS, OB>(p, s);
-    if (ot == 2 && cg == 2) return conv_go<K, 2, 4, 2, ADJ, TS, OB>(p, s);
+    if (ot == 4 && cg == 2) return conv_go<K, 4, 8, 2, 8, ADJ, TS, OB>(p, s);
+    if (ot == 4 && cg == 1) return conv_go<K, 4, 4, 1, 8, ADJ, TS, OB>(p, s);
+    if (ot == 4 && cg == 4) return conv_go<K, 4, 4, 4, 8, ADJ, TS, OB>(p, s);
+    if (ot == 2 && cg == 1) return conv_go<K, 2, 4, 1, 8, ADJ, TS, OB>(p, s);
+    if (ot == 2 && cg == 2) return conv_go<K, 2, 4, 2, 8, ADJ, TS, OB>(p, s);
     if constexpr (K < 5) {
-      if (ot == 2 && cg == 8) return conv_go<K, 2, 4, 8, ADJ, TS, OB>(p, s);
+      if (ot == 2 && cg == 8) return conv_go<K, 2, 4, 8, 8, ADJ, TS, OB>(p, s);
     }
-    if (ot == 1 && cg == 1) return conv_go<K, 1, 4, 1, ADJ, TS, OB>(p, s);
-    if (ot == 1 && cg == 2) return conv_go<K, 1, 4, 2, ADJ, TS, OB>(p, s);
-    if (ot == 1 && cg == 8) return conv_go<K, 1, 4, 8, ADJ, TS, OB>(p, s);
+    if (ot == 1 && cg == 1) return conv_go<K, 1, 4, 1, 8, ADJ, TS, OB>(p, s);
+    if (ot == 1 && cg == 2) return conv_go<K, 1, 4, 2, 8, ADJ, TS, OB>(p, s);
+    if (ot == 1 && cg == 8) return conv_go<K, 1, 4, 8, 8, ADJ, TS, OB>(p, s);
   } else {
-    if (ot == 1 && cg == 8) return conv_go<K, 1, 4, 8, ADJ, TS, OB>(p, s);
-    if (ot == 1 && cg == 4) return conv_go<K, 1, 4, 4, ADJ, TS, OB>(p, s);
-    if (ot == 1 && cg == 2) return conv_go<K, 1, 4, 2, ADJ, TS, OB>(p, s);
-    if (ot == 1 && cg == 1) return conv_go<K, 1, 4, 1, ADJ, TS, OB>(p, s);
+    if (ot == 1 && cg == 8) return conv_go<K, 1, 4, 8, 8, ADJ, TS, OB>(p, s);
+    if (ot == 1 && cg == 4) return conv_go<K, 1, 4, 4, 8, ADJ, TS, OB>(p, s);
+    if (ot == 1 && cg == 2) return conv_go<K, 1, 4, 2, 8, ADJ, TS, OB>(p, s);
+    if (ot == 1 && cg == 1) return conv_go<K, 1, 4, 1, 8, ADJ, TS, OB>(p, s);
   }
   return hipErrorNotSupported;
 }
@@ -909,9 +983,9 @@ f2d_status bank_forward_bf16(const Problem& pr, const f2d_tensor* outs, hipStrea
   p.fo = pr.filter.f_out;
   p.fi = pr.filter.f_in;
   p.o_groups = static_cast<int32_t>((pr.c_out + ot * 16 - 1) / (ot * 16));
-  p.tiles_x = static_cast<int32_t>((im.w + 63) / 64);
+  p.n_img = im.n;
+  p.cols = im.w;
   p.tiles_y = static_cast<int32_t>((pr.rows + kTH - 1) / kTH);
-  p.n_tiles = im.n * p.o_groups * static_cast<int64_t>(p.tiles_x) * p.tiles_y;
   hipError_t e = out.dtype == F2D_BF16 ? conv_by_k<false, uint16_t, true>(p, pr.k, ot, cg, s)
                                        : conv_by_k<false, uint16_t, false>(p, pr.k, ot, cg, s);
   if (e == hipErrorNotSupported) return fail(F2D_EUNSUPPORTED, "bf16 banks: channel counts not supported");
@@ -972,9 +1046,9 @@ f2d_status bank_backward_bf16(const Problem& pr, const f2d_tensor& gout, const f
     p.fo = pr.filter.f_out;
     p.fi = pr.filter.f_in;
     p.o_groups = static_cast<int32_t>((im.c + ot * 16 - 1) / (ot * 16));
-    p.tiles_x = static_cast<int32_t>((im.w + r - p.col0 + 63) / 64);
+    p.n_img = im.n;
+    p.cols = im.w + r - p.col0;
     p.tiles_y = static_cast<int32_t>((p.rows + kTH - 1) / kTH);
-    p.n_tiles = im.n * p.o_groups * static_cast<int64_t>(p.tiles_x) * p.tiles_y;
     hipError_t e = g32 ? conv_by_k<true, float, false>(p, pr.k, ot, cg, s)
                        : conv_by_k<true, uint16_t, false>(p, pr.k, ot, cg, s);
     if (e != hipSuccess) return hip_status(e, "bf16 bank dgrad launch");
