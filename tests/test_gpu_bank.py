@@ -125,6 +125,49 @@ def test_strided_views_take_the_element_staging(gpu_lib, k):
     assert_same(host(gf), oracle.grad_filter(x, g, f.shape, "bank"))
 
 
+BF16_OUT_CASES = [(2, 16, 64, 37, 70), (1, 9, 33, 20, 65), (2, 12, 40, 9, 130), (1, 16, 64, 3, 5),
+                  (1, 16, 48, 4, 64), (1, 16, 64, 1, 1)]
+
+
+@pytest.mark.parametrize("case", BF16_OUT_CASES)
+@pytest.mark.parametrize("k", [1, 3, 5])
+def test_bf16_output_is_bit_exact(gpu_lib, case, k):
+    """BF16 outputs of integer operands: the FP32 sums are exact, so the
+    output must be the oracle's exact value rounded to BF16 (nearest even),
+    bit for bit; ragged widths, 33..64 outputs and 9..16 inputs cover the
+    border, channel and tile-count paths of the 64-output kernels."""
+    n, cin, cout, h, w = case
+    r = wl.rng(36, n, cin, cout, h, w, k)
+    x = r.integers(-8, 9, (n, cin, h, w)).astype(np.float32)
+    f = r.integers(-8, 9, (cout, cin, k, k)).astype(np.float32)
+    xd, xv = bf(x)
+    fd, fv = bf(f)
+    y = gpu_lib.forward(xd, fd, mode="bank", out_dtype=torch.bfloat16)
+    assert y.dtype == torch.bfloat16
+    want = wl.bf16_round(oracle.forward(xv, fv, "bank").astype(np.float32))[1]
+    assert_same(host(y), want.astype(np.float64))
+
+
+@pytest.mark.parametrize("k", [3, 5])
+def test_bf16_output_into_unaligned_view(gpu_lib, k):
+    """BF16 output written into a view with an odd column offset and row pitch:
+    the 16-byte stores must fall back to element stores; the values around the
+    view stay untouched."""
+    r = wl.rng(37, k)
+    x = r.integers(-8, 9, (2, 16, 19, 70)).astype(np.float32)
+    f = r.integers(-8, 9, (64, 16, k, k)).astype(np.float32)
+    xd, xv = bf(x)
+    fd, fv = bf(f)
+    big = torch.full((2, 64, 21, 75), 7.0, device="cuda", dtype=torch.bfloat16)
+    view = big[:, :, 1:20, 3:73]
+    gpu_lib.forward(xd, fd, mode="bank", outs=[view])
+    want = wl.bf16_round(oracle.forward(xv, fv, "bank").astype(np.float32))[1]
+    assert_same(host(view), want.astype(np.float64))
+    outside = big.clone()
+    outside[:, :, 1:20, 3:73] = 7.0
+    assert torch.equal(outside, torch.full_like(big, 7.0))
+
+
 def test_bf16_bank_rows_band(gpu_lib):
     k = 5
     r = wl.rng(32)
@@ -166,12 +209,15 @@ def test_bank_full_size(gpu_lib, k):
     wts = wl.bank_weights(k)
     fd, fv = bf(wts)
     y = gpu_lib.forward(xd, fd, mode="bank")
+    yb = gpu_lib.forward(xd, fd, mode="bank", out_dtype=torch.bfloat16)  # as the benchmark runs it
     torch.cuda.synchronize()
     for nimg in (0, 31):
         xv = host(xd[nimg:nimg + 1])
         for (y0, y1) in [(0, 8), (508, 516), (1016, 1024)]:
             ref = oracle.forward(xv, fv, "bank", rows=(y0, y1))
             assert oracle.rel_l2(host(y[nimg:nimg + 1, :, y0:y1]), ref) <= 1e-5
+            assert oracle.rel_l2(host(yb[nimg:nimg + 1, :, y0:y1]), ref) <= 1e-2
+    del yb
     gi, gf = gpu_lib.backward(xd, fd, gd, mode="bank")
     torch.cuda.synchronize()
     # <A x, g> = <x, A^T g> = <W, W-bar>, accumulated in FP64 one image at a time
