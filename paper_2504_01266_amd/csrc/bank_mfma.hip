@@ -1089,8 +1089,8 @@ hipError_t conv_go(const BankParams& pin, hipStream_t s) {
   BankParams p = pin;
   p.tiles_x = static_cast<int32_t>((p.cols + G::TW - 1) / G::TW);
   p.n_tiles = p.n_img * p.o_groups * static_cast<int64_t>(p.tiles_x) * p.tiles_y;
+  static_assert(G::LDS_ELEMS * 2 <= 160 * 1024, "weights and source tiles exceed LDS");
   const size_t lds = static_cast<size_t>(G::LDS_ELEMS) * 2;
-  if (lds > 160 * 1024) return hipErrorInvalidValue;
   static std::mutex mu;
   static int dev_cached = -1, grid_cached = 0;
   int dev = 0;
@@ -1167,14 +1167,18 @@ hipError_t conv_by_shape(const BankParams& p, int ot, int cg, hipStream_t s) {
   // forward's input channels (<= 16, one tile)
   if constexpr (!ADJ) {
     if (ot == 4 && cg == 2) {
-      // BF16 outputs: the wave-specialised kernel (measured 6% faster at
+      // BF16 outputs: the wave-specialised kernel (measured 4-5% faster at
       // K = 5); FP32 outputs: the eight-wave kernel on 4 x 128 tiles
-      // (the specialised one measured 6% slower there)
+      // (the specialised one measured slower there)
       if constexpr (OB) return conv_ws_go<K, 2>(p, s);
       return conv_go<K, 4, 8, 2, 8, ADJ, TS, OB>(p, s);
     }
     if (ot == 4 && cg == 1) return conv_go<K, 4, 4, 1, 8, ADJ, TS, OB>(p, s);
-    if (ot == 4 && cg == 4) return conv_go<K, 4, 4, 4, 8, ADJ, TS, OB>(p, s);
+    if constexpr (K < 5) {
+      if (ot == 4 && cg == 4) return conv_go<K, 4, 4, 4, 8, ADJ, TS, OB>(p, s);
+    }
+    if (ot == 2 && cg == 4) return conv_go<K, 2, 4, 4, 8, ADJ, TS, OB>(p, s);
+    if (ot == 1 && cg == 4) return conv_go<K, 1, 4, 4, 8, ADJ, TS, OB>(p, s);
     if (ot == 2 && cg == 1) return conv_go<K, 2, 4, 1, 8, ADJ, TS, OB>(p, s);
     if (ot == 2 && cg == 2) return conv_go<K, 2, 4, 2, 8, ADJ, TS, OB>(p, s);
     if constexpr (K < 5) {
@@ -1212,6 +1216,7 @@ bool conv_shape(int64_t ci, int64_t co, int k, int* ot, int* cg) {
   // keep weights + source tile within LDS
   if (*cg == 8 && *ot == 4) *ot = 2;
   if (*cg == 8 && k == 5) *ot = 1;
+  if (*cg == 4 && *ot == 4 && k == 5) *ot = 2;
   return true;
 }
 

@@ -105,6 +105,27 @@ def test_forward_wide_input_bank(gpu_lib, k):
     assert_same(host(y), oracle.forward(xv, fv, "bank"))
 
 
+SHAPE_TABLE = [(3, 40), (8, 64), (16, 17), (16, 64), (24, 40), (32, 16), (32, 32), (32, 64),
+               (40, 20), (64, 16), (64, 40), (64, 64)]
+
+
+@pytest.mark.parametrize("cio", SHAPE_TABLE)
+@pytest.mark.parametrize("k", [1, 3, 5])
+def test_forward_every_tile_shape(gpu_lib, cio, k):
+    """Every (output-channel tile, input-channel group) pair the forward
+    dispatches to, FP32 and BF16 outputs, integer operands: bit-exact."""
+    cin, cout = cio
+    r = wl.rng(38, cin, cout, k)
+    x = r.integers(-4, 5, (1, cin, 11, 70)).astype(np.float32)
+    f = r.integers(-4, 5, (cout, cin, k, k)).astype(np.float32)
+    xd, xv = bf(x)
+    fd, fv = bf(f)
+    ref = oracle.forward(xv, fv, "bank")
+    assert_same(host(gpu_lib.forward(xd, fd, mode="bank")), ref)
+    yb = gpu_lib.forward(xd, fd, mode="bank", out_dtype=torch.bfloat16)
+    assert_same(host(yb), wl.bf16_round(ref.astype(np.float32))[1].astype(np.float64))
+
+
 @pytest.mark.parametrize("k", [3, 5])
 def test_strided_views_take_the_element_staging(gpu_lib, k):
     """Image and upstream gradient as views with a row pitch that is not a
