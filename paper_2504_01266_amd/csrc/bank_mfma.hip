@@ -71,6 +71,9 @@ struct BankParams {
   int32_t tiles_x, tiles_y, o_groups;
   int64_t n_tiles;  // N * o_groups * tiles_y * tiles_x
   int64_t n_img, cols;  // images, and output columns from col0 to cover (tiles_x from the tile width)
+  // row-ring kernel: segments of seg_len tile rows, seg_per_col per tile column
+  int64_t n_segs;
+  int32_t seg_per_col, seg_len;
   // adjoint: output rows start at row0 = -r and columns at col0 <= -r (4-aligned); values
   // on the r-wide frame go to `frame` (frame_plane floats per output plane)
   int64_t col0;
@@ -161,16 +164,16 @@ struct ConvGeom {
 // writes as one 16-byte LDS store.  Loads always use valid addresses; the
 // border rule (clamp, or zero for the adjoint) and the channel padding are
 // applied to the values.
-// SW waves share the staging; staging_nt: unit rounds per wave
-template <typename G, int SW>
+// SW waves share the staging of NR tile rows; staging_nt: unit rounds per wave
+template <typename G, int SW, int NR = G::LH>
 constexpr int staging_nt() {
-  return (G::UNITS + 8 * SW - 1) / (8 * SW);
+  return (NR * (G::UNITS / G::LH) + 8 * SW - 1) / (8 * SW);
 }
 
-template <typename G, int CG, int SW>
+template <typename G, int CG, int SW, int NR = G::LH>
 __device__ __forceinline__ void unit_pos(int it, int wave, int lane, int& ly, int& cg, int& chunk, bool& act) {
   const int u = (it * SW + wave) * 8 + (lane >> 3);
-  act = u < G::UNITS;
+  act = u < NR * (G::UNITS / G::LH);
   const int uu = act ? u : 0;
   chunk = uu % G::CHUNKS;
   const int rest = uu / G::CHUNKS;
@@ -246,17 +249,20 @@ __device__ __forceinline__ void load_chunk(const float* row, int64_t gx0, int64_
   }
 }
 
-template <typename G, int K, int CG, bool ADJ, typename TS, int SW = G::THREADS / 64>
+// Loads for tile rows ly0 .. ly0+NR-1 (of the LH staged rows) of the tile at
+// (oy0, ox0).
+template <typename G, int K, int CG, bool ADJ, typename TS, int SW = G::THREADS / 64, int NR = G::LH>
 __device__ __forceinline__ void stage_load(const BankParams& p, int64_t n, int64_t oy0, int64_t ox0,
-                                           int wave, int lane, Raw<TS, staging_nt<G, SW>()>& st) {
+                                           int wave, int lane, Raw<TS, staging_nt<G, SW, NR>()>& st, int ly0 = 0) {
   const TS* sp = static_cast<const TS*>(p.src) + n * p.s_sn;
   const int j = lane & 7;
   const bool vec = p.s_vec != 0;
 #pragma unroll
-  for (int it = 0; it < staging_nt<G, SW>(); ++it) {
+  for (int it = 0; it < staging_nt<G, SW, NR>(); ++it) {
     int ly, cg, chunk;
     bool act;
-    unit_pos<G, CG, SW>(it, wave, lane, ly, cg, chunk, act);
+    unit_pos<G, CG, SW, NR>(it, wave, lane, ly, cg, chunk, act);
+    ly += ly0;
     int64_t gy = p.row0 + oy0 - G::R + ly;
     gy = gy < 0 ? 0 : (gy >= p.H ? p.H - 1 : gy);
     const int c = cg * 8 + j;
@@ -340,16 +346,25 @@ __device__ __forceinline__ u32x4 transpose8(u32x4 d, int j) {
   return d;
 }
 
-// Transpose and LDS write of staging unit `it` of this wave.
-template <typename G, int K, int CG, bool ADJ, typename TS, int SW = G::THREADS / 64>
+// Transpose and LDS write of staging unit `it` of this wave.  With RING the
+// LDS holds the LH rows as a ring: tile row ly sits in LDS row
+// (slot0 + ly) mod LH.
+template <typename G, int K, int CG, bool ADJ, typename TS, int SW = G::THREADS / 64, int NR = G::LH,
+          bool RING = false>
 __device__ __forceinline__ void stage_store_unit(const BankParams& p, int64_t oy0, int64_t ox0, int wave, int lane,
-                                                 const Raw<TS, staging_nt<G, SW>()>& st, uint16_t* __restrict__ sl,
-                                                 int it) {
+                                                 const Raw<TS, staging_nt<G, SW, NR>()>& st, uint16_t* __restrict__ sl,
+                                                 int it, int ly0 = 0, int slot0 = 0) {
   const int j = lane & 7;
   {
     int ly, cg, chunk;
     bool act;
-    unit_pos<G, CG, SW>(it, wave, lane, ly, cg, chunk, act);
+    unit_pos<G, CG, SW, NR>(it, wave, lane, ly, cg, chunk, act);
+    ly += ly0;
+    int lrow = ly;
+    if constexpr (RING) {
+      lrow = slot0 + ly;
+      lrow -= lrow >= G::LH ? G::LH : 0;
+    }
     bool keep = cg * 8 + j < p.CI;  // padded channels are zero
     if constexpr (ADJ) {
       const int64_t gy = p.row0 + oy0 - G::R + ly;
@@ -366,16 +381,18 @@ __device__ __forceinline__ void stage_store_unit(const BankParams& p, int64_t oy
     }
     if (!keep) d = u32x4{0u, 0u, 0u, 0u};
     d = transpose8(d, j);  // channels cg*8 .. cg*8+7 of pixel chunk*8 + j
-    if (act) *reinterpret_cast<u32x4*>(sl + (ly * G::LW + chunk * 8 + j) * G::PS + cg * 8) = d;
+    if (act) *reinterpret_cast<u32x4*>(sl + (lrow * G::LW + chunk * 8 + j) * G::PS + cg * 8) = d;
   }
 }
 
-template <typename G, int K, int CG, bool ADJ, typename TS, int SW = G::THREADS / 64>
+template <typename G, int K, int CG, bool ADJ, typename TS, int SW = G::THREADS / 64, int NR = G::LH,
+          bool RING = false>
 __device__ __forceinline__ void stage_store(const BankParams& p, int64_t oy0, int64_t ox0, int wave, int lane,
-                                            const Raw<TS, staging_nt<G, SW>()>& st, uint16_t* __restrict__ sl) {
+                                            const Raw<TS, staging_nt<G, SW, NR>()>& st, uint16_t* __restrict__ sl,
+                                            int ly0 = 0, int slot0 = 0) {
 #pragma unroll
-  for (int it = 0; it < staging_nt<G, SW>(); ++it)
-    stage_store_unit<G, K, CG, ADJ, TS, SW>(p, oy0, ox0, wave, lane, st, sl, it);
+  for (int it = 0; it < staging_nt<G, SW, NR>(); ++it)
+    stage_store_unit<G, K, CG, ADJ, TS, SW, NR, RING>(p, oy0, ox0, wave, lane, st, sl, it, ly0, slot0);
 }
 
 // LDS offset (elements) of tap t in the channels-last tile, relative to the
@@ -478,13 +495,14 @@ __device__ __forceinline__ void store_px4(const BankParams& p, int64_t n, int co
 
 // One sweep over k for OTP 16-channel blocks x HP 16-pixel blocks:
 // acc[a][b] += X(pixel block b) * W(channel block a).  w_pass: this lane's
-// weight row of channel block 0; b_lane: this lane's pixel in the source
-// tile.  The operands of step s+1 are read while the MFMAs of step s run (two
-// register sets); the scheduling fences keep the compiler from sinking the
-// reads back next to their uses.  hook(step) runs after each step's MFMAs.
-template <typename G, int K, int CG, int OTP, int HP, typename Hook>
-__device__ __forceinline__ void mfma_sweep(const uint16_t* w_pass, const uint16_t* b_lane, bool hsel, int q,
-                                           f32x4 (&acc)[OTP][HP], Hook&& hook) {
+// weight row of channel block 0; xsrc(step): this lane's pixel operand of
+// step s in LDS (pixel block 0).  The operands of step s+1 are read while the
+// MFMAs of step s run (two register sets); the scheduling fences keep the
+// compiler from sinking the reads back next to their uses.  hook(step) runs
+// after each step's MFMAs.
+template <typename G, int K, int CG, int OTP, int HP, typename Src, typename Hook>
+__device__ __forceinline__ void mfma_sweep(const uint16_t* w_pass, Src&& xsrc, int q, f32x4 (&acc)[OTP][HP],
+                                           Hook&& hook) {
 #pragma unroll
   for (int a = 0; a < OTP; ++a)
 #pragma unroll
@@ -498,10 +516,9 @@ __device__ __forceinline__ void mfma_sweep(const uint16_t* w_pass, const uint16_
 #pragma unroll
     for (int a = 0; a < OTP; ++a)
       wf[set][a] = *reinterpret_cast<const bf16x8*>(w_pass + a * 16 * G::WSTR + 32 * s);
-    // b_step_offset clamps taps past K*K to tap 0, so every read is of
-    // staged pixels; quarters holding a padded k-group (past KG, only in the
-    // last step) zero their operand in registers
-    const uint16_t* bp = b_lane + b_step_offset<G, K, CG>(s, hsel, q);
+    // quarters holding a padded k-group (past KG, only in the last step)
+    // zero their operand in registers
+    const uint16_t* bp = xsrc(step);
     const bool pad = 4 * s + 3 >= G::KG && 4 * s + q >= G::KG;
 #pragma unroll
     for (int b = 0; b < HP; ++b) {
@@ -604,7 +621,11 @@ __global__ __launch_bounds__(64 * NW) void k_bank_conv(BankParams p) {
       // in the last pass, with two source buffers, staging unit S0+u goes
       // after step S0+u (the last step also takes any left over)
       constexpr int S0 = G::STEPS > G::NT ? G::STEPS - G::NT : 0;
-      mfma_sweep<G, K, CG, OTP, HP>(w_pass, b_lane, hsel, q, acc, [&](auto step) __attribute__((always_inline)) {
+      // b_step_offset clamps taps past K*K to tap 0, so every read is of staged pixels
+      auto xsrc = [&](auto step) __attribute__((always_inline)) {
+        return b_lane + b_step_offset<G, K, CG>(decltype(step)::value, hsel, q);
+      };
+      mfma_sweep<G, K, CG, OTP, HP>(w_pass, xsrc, q, acc, [&](auto step) __attribute__((always_inline)) {
         constexpr int s = decltype(step)::value;
         if constexpr (P == NP - 1 && G::NBUF == 2) {
           constexpr int u0 = s - S0, u1 = s == G::STEPS - 1 ? G::NT : s - S0 + 1;
@@ -638,6 +659,109 @@ __global__ __launch_bounds__(64 * NW) void k_bank_conv(BankParams p) {
     oy0 = oy2;
     ox0 = ox2;
     if (G::NBUF == 2) cur ^= 1;
+  }
+}
+
+// ------------------------------------------------------------- row ring --
+//
+// For 33..64 source channels the weights and one source tile fill LDS (no
+// second buffer), and restaging the LH = kTH + K - 1 rows of every 4-row tile
+// costs more than the MFMAs.  Here a work-group walks down a segment of one
+// tile column and keeps the LH source rows in LDS as a ring: the first tile
+// of a segment stages all LH rows, every further tile only its kTH new rows,
+// whose loads are issued before the previous tile's MFMAs.  Tile row ly sits
+// in ring row (slot + ly) mod LH; the MFMA operands of tap row u come from
+// ring row (slot + wrow + u) mod LH.
+template <int K, int OT, int PT, int CG, bool ADJ, typename TS, bool OUT_BF16>
+__global__ __launch_bounds__(512) void k_bank_conv_ring(BankParams p) {
+  using G = ConvGeom<K, OT, PT, CG, 8>;
+  static_assert(CG == 8 && G::NBUF == 1, "64-channel sources with one LDS tile");
+  constexpr int HP = G::HP;
+  constexpr int OTP = OT < 2 ? OT : 2;
+  constexpr int NP = OT / OTP;
+  constexpr int NEW = kTH;  // rows packed per tile after a segment's first
+  constexpr int ROWE = G::LW * G::PS;  // elements per ring row
+  extern __shared__ uint4 smem4[];
+  uint16_t* wl = reinterpret_cast<uint16_t*>(smem4);
+  uint16_t* ring = wl + G::W_ELEMS;
+  const int tid = threadIdx.x;
+  const int lane = tid % 64;
+  const int wave = __builtin_amdgcn_readfirstlane(tid / 64);
+  const int wrow = wave % kTH;
+  const int wcol = (wave / kTH) * (G::TW / G::WPR);
+  const int l16 = lane % 16, q = lane / 16;
+  const uint16_t* w_lane = wl + l16 * G::WSTR + q * 8;
+  const int lane_off = (wcol + l16 + G::XOFF) * G::PS + q * 8;
+
+  const uint32_t spc = static_cast<uint32_t>(p.seg_per_col), tx = static_cast<uint32_t>(p.tiles_x);
+  const uint32_t ngr = static_cast<uint32_t>(p.o_groups);
+  int og_loaded = -1;
+  for (int64_t sg = blockIdx.x; sg < p.n_segs; sg += gridDim.x) {
+    const uint32_t col = static_cast<uint32_t>(sg) / spc, sy = static_cast<uint32_t>(sg) - col * spc;
+    const uint32_t tile_x = col % tx, ng = col / tx;
+    const int og = static_cast<int>(ng % ngr);
+    const int64_t n = ng / ngr;
+    const int ty0 = static_cast<int>(sy) * p.seg_len;
+    const int ty1 = ty0 + p.seg_len < p.tiles_y ? ty0 + p.seg_len : p.tiles_y;
+    const int64_t ox0 = (ADJ ? p.col0 : 0) + static_cast<int64_t>(tile_x) * G::TW;
+    __syncthreads();  // every wave is done with the ring (and weights) of the previous segment
+    if (og != og_loaded) {  // uniform
+      load_weights<G, K, OT, CG, ADJ>(p, og, tid, wl);
+      og_loaded = og;
+    }
+    // Staging positions derive from (wave, lane); passing them through an
+    // empty asm here and in the tile loop keeps the compiler from hoisting
+    // every unit's addresses out of the loops (which spilled ~50 registers).
+    int swave = wave, slane = lane;
+    asm volatile("" : "+s"(swave), "+v"(slane));
+    {
+      Raw<TS, staging_nt<G, 8, G::LH>()> sa;
+      const int64_t oy0 = static_cast<int64_t>(ty0) * kTH;
+      stage_load<G, K, CG, ADJ, TS, 8, G::LH>(p, n, oy0, ox0, swave, slane, sa, 0);
+      stage_store<G, K, CG, ADJ, TS, 8, G::LH, true>(p, oy0, ox0, swave, slane, sa, ring, 0, 0);
+    }
+    int slot = 0;
+    __syncthreads();
+    Raw<TS, staging_nt<G, 8, NEW>()> st;
+    for (int ty = ty0; ty < ty1; ++ty) {
+      const int64_t oy0 = static_cast<int64_t>(ty) * kTH;
+      const bool more = ty + 1 < ty1;  // uniform
+      swave = wave;
+      slane = lane;
+      asm volatile("" : "+s"(swave), "+v"(slane));
+      if (more) stage_load<G, K, CG, ADJ, TS, 8, NEW>(p, n, oy0 + kTH, ox0, swave, slane, st, G::LH - NEW);
+      __builtin_amdgcn_sched_barrier(0);
+      // ring row of this wave's tap row u (uniform), then the lane's pixel
+      const uint16_t* ring_lane = ring + lane_off;
+      const int rbase = slot + wrow;
+      static_for<NP>([&](auto pass) __attribute__((always_inline)) {
+        constexpr int P = decltype(pass)::value;
+        f32x4 acc[OTP][HP];
+        // step s: tap t = s / 2 (32 of the 64 channels per step), channels (s % 2) * 32 + q * 8
+        auto xsrc = [&](auto step) __attribute__((always_inline)) {
+          constexpr int st8 = decltype(step)::value, t = (4 * st8) / CG;
+          int r = rbase + t / K;
+          r -= r >= G::LH ? G::LH : 0;
+          return ring_lane + r * ROWE + ((t % K) * G::PS + ((4 * st8) % CG) * 8);
+        };
+        mfma_sweep<G, K, CG, OTP, HP>(w_lane + P * OTP * 16 * G::WSTR, xsrc, q, acc,
+                                      [](auto) __attribute__((always_inline)) {});
+        const int co0 = (og * NP + P) * OTP * 16 + l16;
+#pragma unroll
+        for (int a = 0; a < OTP; ++a)
+#pragma unroll
+          for (int b = 0; b < HP; ++b)
+            store_px4<ADJ, OUT_BF16>(p, n, co0 + 16 * a, oy0 + wrow, ox0 + wcol + 16 * b + 4 * q, acc[a][b]);
+      });
+      if (more) {  // the oldest kTH ring rows become the next tile's new rows
+        __syncthreads();
+        int nslot = slot + NEW;
+        nslot -= nslot >= G::LH ? G::LH : 0;
+        stage_store<G, K, CG, ADJ, TS, 8, NEW, true>(p, oy0 + kTH, ox0, swave, slane, st, ring, G::LH - NEW, nslot);
+        slot = nslot;
+        __syncthreads();
+      }
+    }
   }
 }
 
@@ -767,8 +891,11 @@ __global__ __launch_bounds__(64 * (kWsMfma + kWsMem)) void k_bank_conv_ws(BankPa
       decode(more ? t_next : t, n2, og2, oy2, ox2);
       {
         f32x4 acc[OTP][HP];
-        mfma_sweep<G, K, CG, OTP, HP>(w_lane, sl0 + cur * G::S_ELEMS + b_off, hsel, q, acc,
-                                      [](auto) __attribute__((always_inline)) {});
+        const uint16_t* b_lane = sl0 + cur * G::S_ELEMS + b_off;
+        auto xsrc = [&](auto step) __attribute__((always_inline)) {
+          return b_lane + b_step_offset<G, K, CG>(decltype(step)::value, hsel, q);
+        };
+        mfma_sweep<G, K, CG, OTP, HP>(w_lane, xsrc, q, acc, [](auto) __attribute__((always_inline)) {});
         // acc[a][b][j] = channel 16a + l16 of the interval, pixel 16b + 4q + j
         char* reg = rb + ri * WG::RBUF_B + (wave % 4) * WG::PAIR_B + (wave / 4) * (WG::REG_B + 256);
 #pragma unroll
@@ -1089,6 +1216,7 @@ hipError_t conv_go(const BankParams& pin, hipStream_t s) {
   BankParams p = pin;
   p.tiles_x = static_cast<int32_t>((p.cols + G::TW - 1) / G::TW);
   p.n_tiles = p.n_img * p.o_groups * static_cast<int64_t>(p.tiles_x) * p.tiles_y;
+  constexpr bool RING = G::NBUF == 1 && CG == 8 && NW == 8;
   static_assert(G::LDS_ELEMS * 2 <= 160 * 1024, "weights and source tiles exceed LDS");
   const size_t lds = static_cast<size_t>(G::LDS_ELEMS) * 2;
   static std::mutex mu;
@@ -1100,9 +1228,12 @@ hipError_t conv_go(const BankParams& pin, hipStream_t s) {
   {
     std::lock_guard<std::mutex> lk(mu);
     if (dev_cached != dev) {
-      auto kern = k_bank_conv<K, OT, PT, CG, NW, ADJ, TS, OB>;
-      e = hipFuncSetAttribute(reinterpret_cast<const void*>(kern), hipFuncAttributeMaxDynamicSharedMemorySize,
-                              static_cast<int>(lds));
+      const void* kern;
+      if constexpr (RING)
+        kern = reinterpret_cast<const void*>(k_bank_conv_ring<K, OT, PT, CG, ADJ, TS, OB>);
+      else
+        kern = reinterpret_cast<const void*>(k_bank_conv<K, OT, PT, CG, NW, ADJ, TS, OB>);
+      e = hipFuncSetAttribute(kern, hipFuncAttributeMaxDynamicSharedMemorySize, static_cast<int>(lds));
       if (e != hipSuccess) return e;
       int per_cu = 0, cus = 0;
       e = hipOccupancyMaxActiveBlocksPerMultiprocessor(&per_cu, kern, G::THREADS, lds);
@@ -1114,11 +1245,30 @@ hipError_t conv_go(const BankParams& pin, hipStream_t s) {
     }
     grid = grid_cached;
   }
-  const int64_t g = p.n_tiles < grid ? p.n_tiles : grid;
-  if (g <= 0) return hipSuccess;
-  hipLaunchKernelGGL((k_bank_conv<K, OT, PT, CG, NW, ADJ, TS, OB>), dim3(static_cast<uint32_t>(g)),
-                     dim3(G::THREADS), lds, s, p);
-  return hipGetLastError();
+  if constexpr (RING) {
+    // segments of at most 32 tile rows, at least ~4 per work-group when the
+    // columns allow, equal length within a column
+    const int64_t cols = p.n_img * p.o_groups * static_cast<int64_t>(p.tiles_x);
+    if (cols <= 0 || p.tiles_y <= 0) return hipSuccess;
+    int64_t spc = (p.tiles_y + 31) / 32;
+    const int64_t want = (4 * static_cast<int64_t>(grid) + cols - 1) / cols;
+    if (want > spc) spc = want < p.tiles_y ? want : p.tiles_y;
+    const int64_t len = (p.tiles_y + spc - 1) / spc;
+    p.seg_len = static_cast<int32_t>(len);
+    p.seg_per_col = static_cast<int32_t>((p.tiles_y + len - 1) / len);
+    p.n_segs = cols * p.seg_per_col;
+    const int64_t g = p.n_segs < grid ? p.n_segs : grid;
+    hipLaunchKernelGGL((k_bank_conv_ring<K, OT, PT, CG, ADJ, TS, OB>), dim3(static_cast<uint32_t>(g)),
+                       dim3(G::THREADS), lds, s, p);
+    return hipGetLastError();
+  }
+  else {
+    const int64_t g = p.n_tiles < grid ? p.n_tiles : grid;
+    if (g <= 0) return hipSuccess;
+    hipLaunchKernelGGL((k_bank_conv<K, OT, PT, CG, NW, ADJ, TS, OB>), dim3(static_cast<uint32_t>(g)),
+                       dim3(G::THREADS), lds, s, p);
+    return hipGetLastError();
+  }
 }
 
 template <int K, int CG>
