@@ -144,10 +144,12 @@ struct ConvGeom {
   static constexpr int PS_MIN = CI8 + 8;
   static constexpr int W_ELEMS = OT * 16 * WSTR;
   static constexpr bool fits2(int ps) { return (W_ELEMS + 2 * LH * LW * ps) * 2 <= LDS_CAP; }
-  static constexpr int PS = fits2(PS_CF) || !fits2(PS_MIN) ? PS_CF : PS_MIN;
+  // 33..64 source channels: one tile, kept as a row ring (k_bank_conv_ring)
+  static constexpr bool RINGED = CG == 8 && NW == 8;
+  static constexpr int PS = RINGED || fits2(PS_CF) || !fits2(PS_MIN) ? PS_CF : PS_MIN;
   static constexpr int S_ELEMS = LH * LW * PS;      // one source tile (16-byte multiple)
   // weights + two source tiles when they fit in the LDS share, else one
-  static constexpr int NBUF = fits2(PS) ? 2 : 1;
+  static constexpr int NBUF = !RINGED && fits2(PS) ? 2 : 1;
   static constexpr int LDS_ELEMS = W_ELEMS + NBUF * S_ELEMS;
   // staging units (row, channel group, 8-column chunk), 8 per wave instruction
   static constexpr int UNITS = LH * CG * CHUNKS;
@@ -664,9 +666,9 @@ __global__ __launch_bounds__(64 * NW) void k_bank_conv(BankParams p) {
 
 // ------------------------------------------------------------- row ring --
 //
-// For 33..64 source channels the weights and one source tile fill LDS (no
-// second buffer), and restaging the LH = kTH + K - 1 rows of every 4-row tile
-// costs more than the MFMAs.  Here a work-group walks down a segment of one
+// For 33..64 source channels a source tile is large (for K = 5 the weights
+// and one tile fill LDS), and restaging the LH = kTH + K - 1 rows of every
+// 4-row tile costs more than the MFMAs.  Here a work-group walks down a segment of one
 // tile column and keeps the LH source rows in LDS as a ring: the first tile
 // of a segment stages all LH rows, every further tile only its kTH new rows,
 // whose loads are issued before the previous tile's MFMAs.  Tile row ly sits
@@ -675,7 +677,7 @@ __global__ __launch_bounds__(64 * NW) void k_bank_conv(BankParams p) {
 template <int K, int OT, int PT, int CG, bool ADJ, typename TS, bool OUT_BF16>
 __global__ __launch_bounds__(512) void k_bank_conv_ring(BankParams p) {
   using G = ConvGeom<K, OT, PT, CG, 8>;
-  static_assert(CG == 8 && G::NBUF == 1, "64-channel sources with one LDS tile");
+  static_assert(G::RINGED && G::NBUF == 1, "64-channel sources with one LDS tile");
   constexpr int HP = G::HP;
   constexpr int OTP = OT < 2 ? OT : 2;
   constexpr int NP = OT / OTP;
@@ -1216,7 +1218,7 @@ hipError_t conv_go(const BankParams& pin, hipStream_t s) {
   BankParams p = pin;
   p.tiles_x = static_cast<int32_t>((p.cols + G::TW - 1) / G::TW);
   p.n_tiles = p.n_img * p.o_groups * static_cast<int64_t>(p.tiles_x) * p.tiles_y;
-  constexpr bool RING = G::NBUF == 1 && CG == 8 && NW == 8;
+  constexpr bool RING = G::RINGED;
   static_assert(G::LDS_ELEMS * 2 <= 160 * 1024, "weights and source tiles exceed LDS");
   const size_t lds = static_cast<size_t>(G::LDS_ELEMS) * 2;
   static std::mutex mu;
