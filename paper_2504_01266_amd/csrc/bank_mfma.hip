@@ -159,11 +159,13 @@ struct ConvGeom {
 };
 
 // Staging of the source tile, channels-last.  A unit = (row ly, channel
-// group cg, 8-column chunk) is handled by 8 lanes: lane j loads the chunk's
-// 8 pixels of channel cg*8 + j (one 16-byte load in the interior, clamped
-// element loads at the left and right image edges), and after an 8 x 8
-// transpose across the 8 lanes it holds the 8 channels of pixel j, which it
-// writes as one 16-byte LDS store.  Loads always use valid addresses; the
+// group cg, 8-column chunk) is handled by the 8 lanes u + 8j of the wave
+// (u = lane & 7 picks the unit of the instruction, j = lane >> 3): lane j
+// loads the chunk's 8 pixels of channel cg*8 + j (one 16-byte load in the
+// interior, clamped element loads at the left and right image edges; the 8
+// lanes of one j read 8 neighbouring chunks, 128 contiguous bytes), and after
+// an 8 x 8 transpose across the unit's lanes it holds the 8 channels of pixel
+// j, which it writes as one 16-byte LDS store.  Loads always use valid addresses; the
 // border rule (clamp, or zero for the adjoint) and the channel padding are
 // applied to the values.
 // SW waves share the staging of NR tile rows; staging_nt: unit rounds per wave
@@ -174,7 +176,7 @@ constexpr int staging_nt() {
 
 template <typename G, int CG, int SW, int NR = G::LH>
 __device__ __forceinline__ void unit_pos(int it, int wave, int lane, int& ly, int& cg, int& chunk, bool& act) {
-  const int u = (it * SW + wave) * 8 + (lane >> 3);
+  const int u = (it * SW + wave) * 8 + (lane & 7);
   act = u < NR * (G::UNITS / G::LH);
   const int uu = act ? u : 0;
   chunk = uu % G::CHUNKS;
@@ -257,7 +259,7 @@ template <typename G, int K, int CG, bool ADJ, typename TS, int SW = G::THREADS 
 __device__ __forceinline__ void stage_load(const BankParams& p, int64_t n, int64_t oy0, int64_t ox0,
                                            int wave, int lane, Raw<TS, staging_nt<G, SW, NR>()>& st, int ly0 = 0) {
   const TS* sp = static_cast<const TS*>(p.src) + n * p.s_sn;
-  const int j = lane & 7;
+  const int j = lane >> 3;
   const bool vec = p.s_vec != 0;
 #pragma unroll
   for (int it = 0; it < staging_nt<G, SW, NR>(); ++it) {
@@ -298,54 +300,29 @@ __device__ __forceinline__ uint32_t lane_xor(uint32_t v, int j) {
   }
 }
 
-// 8 x 8 transpose of 16-bit values across the 8 lanes of a unit: element i
-// of lane j (pair i/2, low half for even i) becomes element j of lane i.
-// Three exchanges, with lanes j^4 (two pairs), j^2 (one pair) and j^1
-// (half a pair).
+// 8 x 8 transpose of 16-bit values across the 8 lanes u, u+8, ..., u+56 of a
+// unit (j = lane >> 3): element i of lane j (pair i/2, low half for even i)
+// becomes element j of lane i.  The exchanges with the lanes 32 and 16 apart
+// swap whole registers (v_permlane32_swap, v_permlane16_swap); the last one,
+// 8 apart, swaps 16-bit halves: a DPP rotate by 8 within the 16-lane row,
+// then a byte permute.  Every lane of the wave must take part.
 __device__ __forceinline__ u32x4 transpose8(u32x4 d, int j) {
-  auto xr = [j](uint32_t v, int m) {
-    return m == 4 ? lane_xor<4>(v, j) : (m == 2 ? lane_xor<2>(v, j) : lane_xor<1>(v, j));
-  };
-  {
-    const bool b = (j & 4) != 0;
-    const uint32_t r0 = xr(b ? d[0] : d[2], 4), r1 = xr(b ? d[1] : d[3], 4);
-    if (b) {
-      d[0] = r0;
-      d[1] = r1;
-    } else {
-      d[2] = r0;
-      d[3] = r1;
-    }
+  const auto a = __builtin_amdgcn_permlane32_swap(d[0], d[2], false, false);
+  const auto b = __builtin_amdgcn_permlane32_swap(d[1], d[3], false, false);
+  const auto c = __builtin_amdgcn_permlane16_swap(a[0], b[0], false, false);
+  const auto e = __builtin_amdgcn_permlane16_swap(a[1], b[1], false, false);
+  const uint32_t x[4] = {c[0], c[1], e[0], e[1]};
+  // low lanes keep their low halves and take the partner's; high lanes the
+  // high halves (bytes 0-3 select the second operand, 4-7 the first)
+  const uint32_t sel = (j & 1) ? 0x03020706u : 0x05040100u;
+  u32x4 r;
+#pragma unroll
+  for (int k = 0; k < 4; ++k) {
+    const uint32_t t = static_cast<uint32_t>(
+        __builtin_amdgcn_mov_dpp(static_cast<int>(x[k]), 0x128 /* row_ror:8 */, 0xf, 0xf, false));
+    r[k] = __builtin_amdgcn_perm(t, x[k], sel);
   }
-  {
-    const bool b = (j & 2) != 0;
-    const uint32_t r0 = xr(b ? d[0] : d[1], 2), r1 = xr(b ? d[2] : d[3], 2);
-    if (b) {
-      d[0] = r0;
-      d[2] = r1;
-    } else {
-      d[1] = r0;
-      d[3] = r1;
-    }
-  }
-  {
-    const bool b = (j & 1) != 0;
-    const uint32_t s0 = b ? ((d[0] & 0xffffu) | (d[1] << 16)) : ((d[0] >> 16) | (d[1] & 0xffff0000u));
-    const uint32_t s1 = b ? ((d[2] & 0xffffu) | (d[3] << 16)) : ((d[2] >> 16) | (d[3] & 0xffff0000u));
-    const uint32_t r0 = xr(s0, 1), r1 = xr(s1, 1);
-    if (b) {
-      d[0] = (r0 & 0xffffu) | (d[0] & 0xffff0000u);
-      d[1] = (r0 >> 16) | (d[1] & 0xffff0000u);
-      d[2] = (r1 & 0xffffu) | (d[2] & 0xffff0000u);
-      d[3] = (r1 >> 16) | (d[3] & 0xffff0000u);
-    } else {
-      d[0] = (d[0] & 0xffffu) | (r0 << 16);
-      d[1] = (d[1] & 0xffffu) | (r0 & 0xffff0000u);
-      d[2] = (d[2] & 0xffffu) | (r1 << 16);
-      d[3] = (d[3] & 0xffffu) | (r1 & 0xffff0000u);
-    }
-  }
-  return d;
+  return r;
 }
 
 // Transpose and LDS write of staging unit `it` of this wave.  With RING the
@@ -356,7 +333,7 @@ template <typename G, int K, int CG, bool ADJ, typename TS, int SW = G::THREADS 
 __device__ __forceinline__ void stage_store_unit(const BankParams& p, int64_t oy0, int64_t ox0, int wave, int lane,
                                                  const Raw<TS, staging_nt<G, SW, NR>()>& st, uint16_t* __restrict__ sl,
                                                  int it, int ly0 = 0, int slot0 = 0) {
-  const int j = lane & 7;
+  const int j = lane >> 3;
   {
     int ly, cg, chunk;
     bool act;
