@@ -145,9 +145,13 @@ struct ConvGeom {
   static constexpr int W_ELEMS = OT * 16 * WSTR;
   static constexpr bool fits2(int ps) { return (W_ELEMS + 2 * LH * LW * ps) * 2 <= LDS_CAP; }
   // 33..64 source channels: one tile, kept as a row ring (k_bank_conv_ring)
+  // of LH rows, or of LH + kTH rows where those fit beside the weights (then
+  // the next tile's rows are packed while the current one computes)
   static constexpr bool RINGED = CG == 8 && NW == 8;
   static constexpr int PS = RINGED || fits2(PS_CF) || !fits2(PS_MIN) ? PS_CF : PS_MIN;
-  static constexpr int S_ELEMS = LH * LW * PS;      // one source tile (16-byte multiple)
+  static constexpr int NSLOT =
+      RINGED && (W_ELEMS + (LH + kTH) * LW * PS) * 2 <= 160 * 1024 ? LH + kTH : LH;
+  static constexpr int S_ELEMS = NSLOT * LW * PS;   // one source tile or the ring (16-byte multiple)
   // weights + two source tiles when they fit in the LDS share, else one
   static constexpr int NBUF = !RINGED && fits2(PS) ? 2 : 1;
   static constexpr int LDS_ELEMS = W_ELEMS + NBUF * S_ELEMS;
@@ -326,8 +330,8 @@ __device__ __forceinline__ u32x4 transpose8(u32x4 d, int j) {
 }
 
 // Transpose and LDS write of staging unit `it` of this wave.  With RING the
-// LDS holds the LH rows as a ring: tile row ly sits in LDS row
-// (slot0 + ly) mod LH.
+// LDS holds the rows as a ring of NSLOT rows: tile row ly sits in LDS row
+// (slot0 + ly) mod NSLOT.
 template <typename G, int K, int CG, bool ADJ, typename TS, int SW = G::THREADS / 64, int NR = G::LH,
           bool RING = false>
 __device__ __forceinline__ void stage_store_unit(const BankParams& p, int64_t oy0, int64_t ox0, int wave, int lane,
@@ -342,7 +346,7 @@ __device__ __forceinline__ void stage_store_unit(const BankParams& p, int64_t oy
     int lrow = ly;
     if constexpr (RING) {
       lrow = slot0 + ly;
-      lrow -= lrow >= G::LH ? G::LH : 0;
+      lrow -= lrow >= G::NSLOT ? G::NSLOT : 0;
     }
     bool keep = cg * 8 + j < p.CI;  // padded channels are zero
     if constexpr (ADJ) {
@@ -649,12 +653,16 @@ __global__ __launch_bounds__(64 * NW) void k_bank_conv(BankParams p) {
 // tile column and keeps the LH source rows in LDS as a ring: the first tile
 // of a segment stages all LH rows, every further tile only its kTH new rows,
 // whose loads are issued before the previous tile's MFMAs.  Tile row ly sits
-// in ring row (slot + ly) mod LH; the MFMA operands of tap row u come from
-// ring row (slot + wrow + u) mod LH.
+// in ring row (slot + ly) mod NSLOT; the MFMA operands of tap row u come from
+// ring row (slot + wrow + u) mod NSLOT.  With NSLOT = LH + kTH the new rows go
+// to the kTH free ring rows, packed unit by unit between the MFMA groups of
+// the last steps (one barrier per tile); with NSLOT = LH they replace the
+// oldest rows after a barrier (packing, then another barrier).
 template <int K, int OT, int PT, int CG, bool ADJ, typename TS, bool OUT_BF16>
 __global__ __launch_bounds__(512) void k_bank_conv_ring(BankParams p) {
   using G = ConvGeom<K, OT, PT, CG, 8>;
   static_assert(G::RINGED && G::NBUF == 1, "64-channel sources with one LDS tile");
+  constexpr bool OVL = G::NSLOT > G::LH;
   constexpr int HP = G::HP;
   constexpr int OTP = OT < 2 ? OT : 2;
   constexpr int NP = OT / OTP;
@@ -713,6 +721,9 @@ __global__ __launch_bounds__(512) void k_bank_conv_ring(BankParams p) {
       // ring row of this wave's tap row u (uniform), then the lane's pixel
       const uint16_t* ring_lane = ring + lane_off;
       const int rbase = slot + wrow;
+      // with the larger ring, the next tile's new rows land in the free rows
+      int nslot = slot + NEW;
+      nslot -= nslot >= G::NSLOT ? G::NSLOT : 0;
       static_for<NP>([&](auto pass) __attribute__((always_inline)) {
         constexpr int P = decltype(pass)::value;
         f32x4 acc[OTP][HP];
@@ -720,11 +731,24 @@ __global__ __launch_bounds__(512) void k_bank_conv_ring(BankParams p) {
         auto xsrc = [&](auto step) __attribute__((always_inline)) {
           constexpr int st8 = decltype(step)::value, t = (4 * st8) / CG;
           int r = rbase + t / K;
-          r -= r >= G::LH ? G::LH : 0;
+          r -= r >= G::NSLOT ? G::NSLOT : 0;
           return ring_lane + r * ROWE + ((t % K) * G::PS + ((4 * st8) % CG) * 8);
         };
+        constexpr int NTN = staging_nt<G, 8, NEW>();
+        constexpr int S0 = G::STEPS > NTN ? G::STEPS - NTN : 0;
         mfma_sweep<G, K, CG, OTP, HP>(w_lane + P * OTP * 16 * G::WSTR, xsrc, q, acc,
-                                      [](auto) __attribute__((always_inline)) {});
+                                      [&](auto step) __attribute__((always_inline)) {
+          constexpr int s8 = decltype(step)::value;
+          if constexpr (OVL && P == NP - 1) {
+            if (more) {  // uniform
+              constexpr int u0 = s8 - S0, u1 = s8 == G::STEPS - 1 ? NTN : s8 - S0 + 1;
+#pragma unroll
+              for (int u = u0 < 0 ? 0 : u0; u < u1; ++u)
+                stage_store_unit<G, K, CG, ADJ, TS, 8, NEW, true>(p, oy0 + kTH, ox0, swave, slane, st, ring, u,
+                                                                 G::LH - NEW, nslot);
+            }
+          }
+        });
         const int co0 = (og * NP + P) * OTP * 16 + l16;
 #pragma unroll
         for (int a = 0; a < OTP; ++a)
@@ -732,13 +756,14 @@ __global__ __launch_bounds__(512) void k_bank_conv_ring(BankParams p) {
           for (int b = 0; b < HP; ++b)
             store_px4<ADJ, OUT_BF16>(p, n, co0 + 16 * a, oy0 + wrow, ox0 + wcol + 16 * b + 4 * q, acc[a][b]);
       });
-      if (more) {  // the oldest kTH ring rows become the next tile's new rows
-        __syncthreads();
-        int nslot = slot + NEW;
-        nslot -= nslot >= G::LH ? G::LH : 0;
-        stage_store<G, K, CG, ADJ, TS, 8, NEW, true>(p, oy0 + kTH, ox0, swave, slane, st, ring, G::LH - NEW, nslot);
+      if (more) {
+        __syncthreads();  // (larger ring: the new rows are packed; all reads of the oldest rows done)
+        if constexpr (!OVL) {  // the oldest kTH ring rows become the next tile's new rows
+          stage_store<G, K, CG, ADJ, TS, 8, NEW, true>(p, oy0 + kTH, ox0, swave, slane, st, ring, G::LH - NEW,
+                                                      nslot);
+          __syncthreads();
+        }
         slot = nslot;
-        __syncthreads();
       }
     }
   }
