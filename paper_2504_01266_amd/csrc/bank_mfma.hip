@@ -12,14 +12,21 @@
 //                the weights of its current output group (all taps x channels
 //                of OT*16 output channels) in LDS and walks 4 x (16*PT)-pixel
 //                tiles; the next tile's global loads are in flight during the
-//                MFMA loop and land in the second LDS tile buffer after it.
-//                Each wave owns one tile row, half of its pixels, and
-//                OT x PT/2 16x16 accumulator blocks.  Forward: clamp-to-edge borders.
-//                Adjoint in the image (dgrad): zero borders and the
-//                transposed, flipped weights, evaluated on the image plus an
-//                r-wide frame whose values are then folded onto the edge
-//                pixels (the exact clamp adjoint).  Upstream gradients given
-//                in FP32 are rounded to BF16 (nearest even) while staged.
+//                MFMA sweeps and, with two tile buffers, are packed into the
+//                idle one between the MFMA groups of the last steps.  Each
+//                wave owns a share of one tile row and sweeps k once per
+//                32-channel pass.  Forward: clamp-to-edge borders.  Adjoint
+//                in the image (dgrad): zero borders and the transposed,
+//                flipped weights, evaluated on the image plus an r-wide frame
+//                whose values are then folded onto the edge pixels (the exact
+//                clamp adjoint).  Upstream gradients given in FP32 are rounded
+//                to BF16 (nearest even) while staged.
+//  k_bank_conv_ring  the same for 33..64 source channels: a work-group walks
+//                down a column segment keeping the staged rows as a ring, so
+//                every tile after the first stages only its 4 new rows.
+//  k_bank_conv_ws  the forward from 9..16 to 33..64 channels with BF16 outputs,
+//                with the memory traffic on separate waves: MFMA waves read LDS only,
+//                memory waves stage tiles and store results from LDS.
 //  k_bank_wgrad  W-bar[o][i][u][v] = sum_p G[o][p] * X[i][shift_uv(p)]: for
 //                every tap a 16(o) x 16(i) block contracted over 32-pixel
 //                steps; each staged X row is read once as a window and the
@@ -44,10 +51,8 @@ typedef __bf16 bf16x8 __attribute__((ext_vector_type(8)));
 typedef float f32x4 __attribute__((ext_vector_type(4)));
 typedef uint32_t u32x4 __attribute__((ext_vector_type(4)));
 typedef uint32_t u32x2 __attribute__((ext_vector_type(2)));
-typedef uint16_t u16x2 __attribute__((ext_vector_type(2)));
 
 constexpr int kThreads = 256;      // wgrad work-group
-constexpr int kWaves = 4;
 constexpr int kTH = 4;             // conv tile rows
 
 // f(integral_constant<int, 0>) ... f(integral_constant<int, N-1>), in order
@@ -526,7 +531,8 @@ __device__ __forceinline__ void mfma_sweep(const uint16_t* w_pass, Src&& xsrc, i
 
 // Persistent work-group over (image, output group, kTH x TW tile).  Each wave
 // computes OT*16 output channels x HP*16 pixels of one tile row in NP passes
-// of OTP*16 channels (one full sweep over k per pass, 32 accumulators).
+// of OTP*16 channels (one full sweep over k per pass, OTP x HP 16x16
+// accumulator blocks).
 //
 //  * the loads of tile t+1 are issued when tile t starts; with two source
 //    buffers, tile t+1 is packed into the idle buffer unit by unit between
