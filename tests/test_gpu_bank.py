@@ -189,6 +189,29 @@ def test_bf16_output_into_unaligned_view(gpu_lib, k):
     assert torch.equal(outside, torch.full_like(big, 7.0))
 
 
+@pytest.mark.parametrize("k", [3, 5])
+def test_row_ring_segments_bit_exact(gpu_lib, k):
+    """64-channel sources (grad_input of a 16 -> 64 bank, and a 64 -> 16
+    forward) on 2 x 512^2 images: enough tiles that the row-ring kernel's
+    column segments hold several tiles each, so the packing of only the new
+    rows (and, for 3x3, the larger ring packed between MFMA steps) is compared
+    element by element; integer operands, bit-exact."""
+    r = wl.rng(40, k)
+    x = r.integers(-4, 5, (2, 16, 512, 512)).astype(np.float32)
+    f = r.integers(-4, 5, (64, 16, k, k)).astype(np.float32)
+    g = r.integers(-4, 5, (2, 64, 512, 512)).astype(np.float32)
+    xd, xv = bf(x)
+    fd, fv = bf(f)
+    gd, gv = bf(g)
+    gi, _ = gpu_lib.backward(xd, fd, gd, mode="bank", need_filter=False)
+    assert_same(host(gi), oracle.grad_input(gv, fv, x.shape, "bank"))
+    x64 = r.integers(-4, 5, (2, 64, 512, 512)).astype(np.float32)
+    f64 = r.integers(-4, 5, (16, 64, k, k)).astype(np.float32)
+    x64d, x64v = bf(x64)
+    f64d, f64v = bf(f64)
+    assert_same(host(gpu_lib.forward(x64d, f64d, mode="bank")), oracle.forward(x64v, f64v, "bank"))
+
+
 def test_bf16_bank_rows_band(gpu_lib):
     k = 5
     r = wl.rng(32)
