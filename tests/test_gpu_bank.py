@@ -212,6 +212,23 @@ def test_row_ring_segments_bit_exact(gpu_lib, k):
     assert_same(host(gpu_lib.forward(x64d, f64d, mode="bank")), oracle.forward(x64v, f64v, "bank"))
 
 
+@pytest.mark.parametrize("k", [3, 5])
+def test_forward_many_tiles_per_work_group_bit_exact(gpu_lib, k):
+    """16 -> 64 channels on 2 x 512^2 images: thousands of tiles, so every
+    persistent work-group of the forward kernels (the wave-specialised one
+    for BF16 outputs, the eight-wave one for FP32) walks several tiles and
+    its prefetch / buffer alternation is compared element by element."""
+    r = wl.rng(41, k)
+    x = r.integers(-4, 5, (2, 16, 512, 512)).astype(np.float32)
+    f = r.integers(-4, 5, (64, 16, k, k)).astype(np.float32)
+    xd, xv = bf(x)
+    fd, fv = bf(f)
+    ref = oracle.forward(xv, fv, "bank")
+    assert_same(host(gpu_lib.forward(xd, fd, mode="bank")), ref)
+    yb = gpu_lib.forward(xd, fd, mode="bank", out_dtype=torch.bfloat16)
+    assert_same(host(yb), wl.bf16_round(ref.astype(np.float32))[1].astype(np.float64))
+
+
 def test_bf16_bank_rows_band(gpu_lib):
     k = 5
     r = wl.rng(32)
