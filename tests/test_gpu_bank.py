@@ -192,7 +192,7 @@ def test_bf16_output_into_unaligned_view(gpu_lib, k):
 @pytest.mark.parametrize("k", [3, 5])
 def test_row_ring_segments_bit_exact(gpu_lib, k):
     """64-channel sources (grad_input of a 16 -> 64 bank, and a 64 -> 16
-    forward) on 2 x 512^2 images: enough tiles that the row-ring kernel's
+    forward; also grad_filter) on 2 x 512^2 images: enough tiles that the row-ring kernel's
     column segments hold several tiles each, so the packing of only the new
     rows (and, for 3x3, the larger ring packed between MFMA steps) is compared
     element by element; integer operands, bit-exact."""
@@ -205,6 +205,10 @@ def test_row_ring_segments_bit_exact(gpu_lib, k):
     gd, gv = bf(g)
     gi, _ = gpu_lib.backward(xd, fd, gd, mode="bank", need_filter=False)
     assert_same(host(gi), oracle.grad_input(gv, fv, x.shape, "bank"))
+    # grad_filter over the same images: each persistent unit walks two tiles;
+    # the sums (|.| < 2^24) are exact in FP32, so bit-exact too
+    _, gf = gpu_lib.backward(xd, fd, gd, mode="bank", need_input=False)
+    assert_same(host(gf), oracle.grad_filter(xv, gv, f.shape, "bank"))
     x64 = r.integers(-4, 5, (2, 64, 512, 512)).astype(np.float32)
     f64 = r.integers(-4, 5, (16, 64, k, k)).astype(np.float32)
     x64d, x64v = bf(x64)
