@@ -663,7 +663,9 @@ __global__ __launch_bounds__(64 * NW) void k_bank_conv(BankParams p) {
 // ring row (slot + wrow + u) mod NSLOT.  With NSLOT = LH + kTH the new rows go
 // to the kTH free ring rows, packed unit by unit between the MFMA groups of
 // the last steps (one barrier per tile); with NSLOT = LH they replace the
-// oldest rows after a barrier (packing, then another barrier).
+// oldest rows once no wave reads them any more: for K > kTH packed between
+// the MFMA groups of the last tap rows' steps, after a barrier (two barriers
+// per tile), else after the sweep, between two barriers.
 template <int K, int OT, int PT, int CG, bool ADJ, typename TS, bool OUT_BF16>
 __global__ __launch_bounds__(512) void k_bank_conv_ring(BankParams p) {
   using G = ConvGeom<K, OT, PT, CG, 8>;
@@ -674,6 +676,14 @@ __global__ __launch_bounds__(512) void k_bank_conv_ring(BankParams p) {
   constexpr int NP = OT / OTP;
   constexpr int NEW = kTH;  // rows packed per tile after a segment's first
   constexpr int ROWE = G::LW * G::PS;  // elements per ring row
+  // LH-row ring: steps run tap-row major, 2K per tap row (two per tap).
+  // Wave row wrow reads ring row wrow + u for tap row u, so from the first
+  // step of tap row kTH on no wave reads the kTH oldest rows; where that
+  // step falls inside the sweep (LATE), a barrier there lets the new rows
+  // replace them, packed between the MFMA groups of the remaining steps.
+  static_assert(CG == 8 && G::STEPS == 2 * K * K, "two steps per tap");
+  constexpr int SB = 2 * K * kTH;
+  constexpr bool LATE = !OVL && SB < G::STEPS;
   extern __shared__ uint4 smem4[];
   uint16_t* wl = reinterpret_cast<uint16_t*>(smem4);
   uint16_t* ring = wl + G::W_ELEMS;
@@ -745,9 +755,11 @@ __global__ __launch_bounds__(512) void k_bank_conv_ring(BankParams p) {
         mfma_sweep<G, K, CG, OTP, HP>(w_lane + P * OTP * 16 * G::WSTR, xsrc, q, acc,
                                       [&](auto step) __attribute__((always_inline)) {
           constexpr int s8 = decltype(step)::value;
-          if constexpr (OVL && P == NP - 1) {
+          if constexpr ((OVL || LATE) && P == NP - 1) {
             if (more) {  // uniform
-              constexpr int u0 = s8 - S0, u1 = s8 == G::STEPS - 1 ? NTN : s8 - S0 + 1;
+              if constexpr (LATE && s8 == SB - 1) __syncthreads();
+              constexpr int SS = OVL ? S0 : (SB > S0 ? SB : S0);
+              constexpr int u0 = s8 - SS, u1 = s8 == G::STEPS - 1 ? NTN : s8 - SS + 1;
 #pragma unroll
               for (int u = u0 < 0 ? 0 : u0; u < u1; ++u)
                 stage_store_unit<G, K, CG, ADJ, TS, 8, NEW, true>(p, oy0 + kTH, ox0, swave, slane, st, ring, u,
@@ -763,8 +775,8 @@ __global__ __launch_bounds__(512) void k_bank_conv_ring(BankParams p) {
             store_px4<ADJ, OUT_BF16>(p, n, co0 + 16 * a, oy0 + wrow, ox0 + wcol + 16 * b + 4 * q, acc[a][b]);
       });
       if (more) {
-        __syncthreads();  // (larger ring: the new rows are packed; all reads of the oldest rows done)
-        if constexpr (!OVL) {  // the oldest kTH ring rows become the next tile's new rows
+        __syncthreads();  // (OVL, LATE: the new rows are packed; all reads of the oldest rows done)
+        if constexpr (!OVL && !LATE) {  // the oldest kTH ring rows become the next tile's new rows
           stage_store<G, K, CG, ADJ, TS, 8, NEW, true>(p, oy0 + kTH, ox0, swave, slane, st, ring, G::LH - NEW,
                                                       nslot);
           __syncthreads();
