@@ -310,6 +310,24 @@ def profile_run(torch, B, wl, steps):
                       "copy_bytes_read": a.numel() * 4, "copy_bytes_written": b.numel() * 4}), flush=True)
 
 
+def profile_bank_run(torch, B, steps):
+    """Counter-profiling run of the BF16 filter bank, 32x16x1024^2 -> 64
+    channels, 5x5: `steps` x (forward with BF16 outputs + grad_input +
+    grad_filter), on the suite's seeded tensors."""
+    gen = torch.Generator(device="cuda").manual_seed(5)
+    xb = torch.randn((32, 16, 1024, 1024), generator=gen, device="cuda").to(torch.bfloat16)
+    gb = torch.randn((32, 64, 1024, 1024), generator=gen, device="cuda").to(torch.bfloat16)
+    yb = torch.empty((32, 64, 1024, 1024), dtype=torch.bfloat16, device="cuda")
+    wk = (torch.randn((64, 16, 5, 5), generator=gen, device="cuda") *
+          float(np.sqrt(2.0 / (16 * 25)))).to(torch.bfloat16)
+    ws = torch.empty(B.backward_workspace(xb, wk, mode="bank"), dtype=torch.uint8, device="cuda")
+    for _ in range(steps):
+        B.forward(xb, wk, mode="bank", outs=[yb])
+        B.backward(xb, wk, gb, mode="bank", workspace=ws)
+    torch.cuda.synchronize()
+    print(json.dumps({"profile": "bank-bf16-5x5", "steps": steps}), flush=True)
+
+
 def main():
     ap = argparse.ArgumentParser(description=__doc__, formatter_class=argparse.RawDescriptionHelpFormatter)
     ap.add_argument("--gpus", type=int, default=1)
@@ -321,6 +339,8 @@ def main():
     ap.add_argument("--no-cpu", action="store_true", help="skip the oracle baseline")
     ap.add_argument("--profile", action="store_true",
                     help="counter-profiling run: headline kernel --steps times + a 1 GiB copy")
+    ap.add_argument("--profile-bank", action="store_true",
+                    help="counter-profiling run: BF16 bank 5x5 forward + backward --steps times")
     args = ap.parse_args()
     if args.gpus != 1:
         print(f"bench.py measures one GPU only (got --gpus {args.gpus}); the filter runs on one "
@@ -337,6 +357,9 @@ def main():
     torch.cuda.set_device(0)
     if args.profile:
         profile_run(torch, B, wl, args.steps)
+        return
+    if args.profile_bank:
+        profile_bank_run(torch, B, args.steps)
         return
     log("bench: headline sobel 8k")
     hd = headline(torch, B, wl, args.steps, args.warmup)
