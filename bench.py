@@ -9,8 +9,8 @@ over the whole frame (a single kernel), inputs resident in HBM.
 Metric: Mpix*taps/s, where a pixel is one output value of one channel and
 taps are the multiply-adds per output value (18 for the Sobel pair: two dense
 3x3 filters, zeros counted).  The suite adds the other workloads (plain FP32
-forward, FP32 forward+backward, ragged batch, BF16 filter bank) with their
-ratio to the plain FP32 forward.
+forward, FP32 forward+backward, separable FP32 forward, ragged batch, BF16
+filter bank) with their ratio to the plain FP32 forward.
 
 Prints ONE JSON line.  Usage: python bench.py [--gpus 1] [--steps K] [--warmup W]
 """
@@ -210,7 +210,25 @@ def suite(torch, B, wl, reps):
                                             "achieved": round(2.0 * pt3 / (ms_fb * 1e-3) / 1e12, 2),
                                             "peak": FP32_VALU_PEAK_TFLOPS, "unit": "TFLOP/s",
                                             "frac": round(2.0 * pt3 / (ms_fb * 1e-3) / 1e12 / FP32_VALU_PEAK_TFLOPS, 4)}}
-    del xd, out, gd, gi, ws
+    # separable fast path on the same images: the 9x9 normalised Gaussian
+    # (sigma 2) as g g^T, 2K = 18 multiply-adds per output, against the
+    # direct K x K path with the same filter
+    g9 = wl.gaussian_factor(9, 2.0)
+    gk = torch.from_numpy(g9).cuda()
+    fgg = torch.from_numpy(np.outer(g9, g9).astype(np.float32)).cuda()
+    ms_sep = t.per_call_ms(lambda: B.forward_separable(xd, gk, gk, out=out), reps)
+    ms_dir = t.per_call_ms(lambda: B.forward(xd, fgg, outs=[out]), reps)
+    ps = xs.size * 18
+    res["separable_f32_fwd"] = {"shape": "16x3x2048x2048 f32, 9x9 Gaussian as g g^T (18 taps per output)",
+                                "ms": round(ms_sep, 4), "direct_ms": round(ms_dir, 4),
+                                "speedup_vs_direct": round(ms_dir / ms_sep, 3),
+                                "mpix_taps_s": round(ps / (ms_sep * 1e-3) / 1e6, 1),
+                                "vs_plain_fwd": round(ps / (ms_sep * 1e-3) / 1e6 / plain, 3),
+                                "roofline": {"bound": "hbm",
+                                             "achieved": round(xs.size * 8 / (ms_sep * 1e-3) / 1e9, 1),
+                                             "peak": HBM_PEAK_GBS, "unit": "GB/s",
+                                             "frac": round(xs.size * 8 / (ms_sep * 1e-3) / 1e9 / HBM_PEAK_GBS, 4)}}
+    del xd, out, gd, gi, ws, gk, fgg
     torch.cuda.empty_cache()
 
     # ragged batch: 64 images, H, W uniform in [256, 4096], 3 channels, 7x7 each

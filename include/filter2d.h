@@ -130,6 +130,29 @@ f2d_status filter2d_forward(const f2d_tensor* image, const f2d_filter* filter,
                             void* stream);
 
 /*
+ * filter2d_forward_separable -- filter2d_forward for a rank-one filter
+ * F[u][v] = a[u] * b[v] (the equation at the top of this file with that F),
+ * computed as a row pass then a column pass: 2K multiply-adds per output
+ * instead of K^2.
+ *
+ *   image   [N][C][H][W] F32
+ *   a, b    DEVICE pointers to k floats each: a weighs the row offset u - r,
+ *           b the column offset v - r (a normalised Gaussian is g g^T)
+ *   k       odd, 1..15 (F2D_EUNSUPPORTED for larger odd k)
+ *   opts    border CLAMP, channels SHARED (one a, b for every channel),
+ *           epilogue NONE; variant ignored; row_begin / row_end select a band
+ *           of output rows exactly as for filter2d_forward
+ *   out     [N][C][rows][W] F32, rows = row_end - row_begin
+ * Every output is sum_u a[u] * (sum_v b[v] * X[..]) in FP32 with the clamp
+ * applied to the source rows and columns, so it equals filter2d_forward with
+ * F = a b^T up to FP32 rounding (not bitwise).  Ownership, validation and
+ * errors as for filter2d_forward; other dtypes and channel modes return
+ * F2D_EUNSUPPORTED.
+ */
+f2d_status filter2d_forward_separable(const f2d_tensor* image, const float* a, const float* b, int32_t k,
+                                      const f2d_opts* opts, const f2d_tensor* out, void* stream);
+
+/*
  * Workspace bytes that filter2d_backward needs for these arguments (device
  * memory, caller-allocated, any alignment >= 256 bytes).  Returns 0 for
  * invalid arguments.

@@ -75,6 +75,7 @@ def load():
     i32, i64, vp, sz = ctypes.c_int32, ctypes.c_int64, ctypes.c_void_p, ctypes.c_size_t
     sigs = {
         "filter2d_forward": (i32, [_P(F2dTensor), _P(F2dFilter), _P(F2dOpts), _P(F2dTensor), i32, vp]),
+        "filter2d_forward_separable": (i32, [_P(F2dTensor), vp, vp, i32, _P(F2dOpts), _P(F2dTensor), vp]),
         "filter2d_backward_workspace": (sz, [_P(F2dTensor), _P(F2dFilter), _P(F2dOpts)]),
         "filter2d_backward": (i32, [_P(F2dTensor), _P(F2dFilter), _P(F2dTensor), i32, _P(F2dOpts),
                                     _P(F2dTensor), vp, vp, sz, vp]),
@@ -180,6 +181,26 @@ def forward(image, filt, mode="shared", epilogue=EPI_NONE, rows=None, outs=None,
     _check(lib.filter2d_forward(ctypes.byref(tensor_desc(image)), ctypes.byref(fd),
                                 ctypes.byref(opts), descs, len(outs), _stream()))
     return outs if m == DEPTHWISE else outs[0]
+
+
+def forward_separable(image, a, b, rows=None, out=None):
+    """Y = filter(X) for the rank-one filter a b^T (FP32, SHARED), on the
+    current stream.  a, b: 1-D device tensors of k float32 taps."""
+    lib = load()
+    image = _as4(image)
+    if a.dim() != 1 or b.dim() != 1 or a.numel() != b.numel():
+        raise ValueError("a and b must be 1-D with the same length k")
+    if a.dtype != torch.float32 or b.dtype != torch.float32 or not a.is_contiguous() or not b.is_contiguous():
+        raise ValueError("a and b must be contiguous float32")
+    n, c, h, w = image.shape
+    r0, r1 = (0, h) if rows is None else rows
+    if out is None:
+        out = torch.empty((n, c, r1 - r0, w), dtype=torch.float32, device=image.device)
+    opts = make_opts("shared", EPI_NONE, (r0, r1))
+    _check(lib.filter2d_forward_separable(ctypes.byref(tensor_desc(image)), ctypes.c_void_p(a.data_ptr()),
+                                          ctypes.c_void_p(b.data_ptr()), a.numel(), ctypes.byref(opts),
+                                          ctypes.byref(tensor_desc(out)), _stream()))
+    return out
 
 
 def backward_workspace(image, filt, mode="shared"):

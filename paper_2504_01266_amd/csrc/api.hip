@@ -289,6 +289,22 @@ f2d_status filter2d_forward(const f2d_tensor* image, const f2d_filter* filter, c
   return run_forward(pr, outs, n_outs, static_cast<hipStream_t>(stream));
 }
 
+f2d_status filter2d_forward_separable(const f2d_tensor* image, const float* a, const float* b, int32_t k,
+                                     const f2d_opts* opts, const f2d_tensor* out, void* stream) {
+  if (!a || !b) return fail(F2D_EINVAL, "separable: factor a or b is NULL");
+  if (opts && opts->channels != F2D_CH_SHARED)
+    return fail(F2D_EUNSUPPORTED, "separable: SHARED channel mode only");
+  const f2d_filter filter{a, F2D_F32, 1, 1, k};
+  Problem pr;
+  f2d_status s = check_common(image, &filter, opts, &pr);
+  if (s) return s;
+  if (image->dtype != F2D_F32) return fail(F2D_EUNSUPPORTED, "separable: f32 images only");
+  if (k > 15) return fail(F2D_EUNSUPPORTED, "separable: k=%d (1..15 are built)", k);
+  s = check_outputs(pr, out, 1, "out");
+  if (s) return s;
+  return run_forward_separable(pr, a, b, *out, static_cast<hipStream_t>(stream));
+}
+
 size_t filter2d_backward_workspace(const f2d_tensor* image, const f2d_filter* filter,
                                    const f2d_opts* opts) {
   Problem pr;

@@ -45,6 +45,10 @@ f2d_status run_forward(const Problem& pr, const f2d_tensor* outs, int32_t n_outs
 f2d_status autotune_forward(const Problem& pr, const f2d_tensor* outs, int32_t n_outs, int32_t reps,
                             hipStream_t s, int32_t* best);
 
+// separable_f32.hip (a, b: device pointers to k floats each)
+f2d_status run_forward_separable(const Problem& pr, const float* a, const float* b, const f2d_tensor& out,
+                                 hipStream_t s);
+
 // backward.hip
 size_t backward_workspace(const Problem& pr);
 f2d_status run_backward(const Problem& pr, const f2d_tensor* grad_outs, int32_t n_grad_outs,

@@ -37,6 +37,24 @@ def gaussian_taps(k=5, sigma=1.0):
     return t.astype(np.float32)
 
 
+def gaussian_factor(k=9, sigma=2.0):
+    """The 1-D factor g / sum(g) of a normalised sampled Gaussian (float64,
+    rounded once to float32): the 2-D filter is its outer product with
+    itself."""
+    r = (k - 1) // 2
+    d = np.arange(-r, r + 1, dtype=np.float64)
+    g = np.exp(-(d * d) / (2.0 * sigma * sigma))
+    return (g / g.sum()).astype(np.float32)
+
+
+def separable_factors(seed, k):
+    """Random float32 factors a, b with taps N(0, 1/k) (a rank-one filter
+    a b^T with taps of variance 1/k^2, like the 7x7 and 9x9 workloads)."""
+    r = rng(seed, k, 4242)
+    return (r.standard_normal(k) / np.sqrt(k)).astype(np.float32), \
+        (r.standard_normal(k) / np.sqrt(k)).astype(np.float32)
+
+
 SOBEL_X = np.array([[-1, 0, 1], [-2, 0, 2], [-1, 0, 1]], dtype=np.int32)
 SOBEL_Y = SOBEL_X.T.copy()
 

@@ -110,6 +110,28 @@ def test_forward_rejects_on_the_host(lib, case):
     assert frag.lower() in B.last_error().lower()
 
 
+SEP_CASES = [
+    # (description, image, a, k, opts, out, expected status, message fragment)
+    ("null factor", _img(), None, 3, B.make_opts(), _img(), B.EINVAL, "NULL"),
+    ("even K", _img(), FAKE, 4, B.make_opts(), _img(), B.EINVAL, "odd"),
+    ("K beyond the built range", _img(), FAKE, 17, B.make_opts(), _img(), B.EUNSUPPORTED, "1..15"),
+    ("u8 image", _img(B.U8), FAKE, 3, B.make_opts(), _img(B.I32), B.EINVAL, "int32"),
+    ("depthwise mode", _img(), FAKE, 3, B.make_opts("depthwise"), _img(), B.EUNSUPPORTED, "SHARED"),
+    ("wrong output shape", _img(), FAKE, 3, B.make_opts(), _img(w=39), B.EINVAL, "shape"),
+    ("band outside image", _img(h=32), FAKE, 3, B.make_opts(rows=(10, 40)), _img(h=30), B.EINVAL,
+     "outside"),
+]
+
+
+@pytest.mark.parametrize("case", SEP_CASES, ids=[c[0] for c in SEP_CASES])
+def test_forward_separable_rejects_on_the_host(lib, case):
+    _, image, a, k, opts, out, status, frag = case
+    st = lib.filter2d_forward_separable(ctypes.byref(image), a, FAKE, k, ctypes.byref(opts),
+                                        ctypes.byref(out), None)
+    assert st == status
+    assert frag.lower() in B.last_error().lower()
+
+
 def test_backward_validation_on_the_host(lib):
     image, filt = _img(), _filt(k=3)
     opts = B.make_opts()
