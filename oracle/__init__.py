@@ -47,6 +47,8 @@ def _load():
     lib = ctypes.CDLL(_LIB_PATH)
     lib.oracle_forward_f64.argtypes = [_dp, _i64, _i64, _i64, _i64, _dp, _i64, _i64, _i64, _i32,
                                        _i64, _i64, _dp]
+    lib.oracle_forward_zero_f64.argtypes = [_dp, _i64, _i64, _i64, _i64, _dp, _i64, _i64, _i64,
+                                            _i32, _i64, _i64, _dp]
     lib.oracle_forward_i64.argtypes = [_lp, _i64, _i64, _i64, _i64, _lp, _i64, _i64, _i64, _i32,
                                        _i64, _i64, _lp]
     lib.oracle_sumsq_i64.argtypes = [_lp, _lp, _i64, _lp]
@@ -54,7 +56,7 @@ def _load():
                                           _i32, _dp]
     lib.oracle_grad_filter_f64.argtypes = [_dp, _dp, _i64, _i64, _i64, _i64, _i64, _i64, _i64,
                                            _i32, _dp]
-    for name in ("oracle_forward_f64", "oracle_forward_i64", "oracle_sumsq_i64",
+    for name in ("oracle_forward_f64", "oracle_forward_zero_f64", "oracle_forward_i64", "oracle_sumsq_i64",
                  "oracle_grad_input_f64", "oracle_grad_filter_f64", "oracle_num_threads"):
         getattr(lib, name).restype = ctypes.c_int
     _lib = lib
@@ -94,10 +96,14 @@ def _out_channels(C, FO, mode):
     return C if mode == SHARED else FO
 
 
-def forward(x, f, mode="shared", rows=None):
+def forward(x, f, mode="shared", rows=None, border="clamp"):
     """FP64 forward filter.  x: [N][C][H][W] (or [H][W]); f: [FO][FI][K][K] (or [K][K]).
     rows=(y0, y1) restricts the output to rows y0..y1-1 (clamping is still done
-    with respect to the whole array).  Returns float64 [N][C_out][y1-y0][W]."""
+    with respect to the whole array).  border="zero": out-of-image neighbours
+    contribute nothing (the paper's sharpen, Section 4.2.4).  Returns float64
+    [N][C_out][y1-y0][W]."""
+    if border not in ("clamp", "zero"):
+        raise ValueError("border must be 'clamp' or 'zero'")
     m = _mode(mode)
     x = np.ascontiguousarray(_as4(x), dtype=np.float64)
     f = np.ascontiguousarray(_filt4(f), dtype=np.float64)
@@ -105,10 +111,11 @@ def forward(x, f, mode="shared", rows=None):
     FO, FI, K, _ = f.shape
     y0, y1 = (0, H) if rows is None else rows
     out = np.empty((N, _out_channels(C, FO, m), y1 - y0, W), np.float64)
-    rc = _load().oracle_forward_f64(x.ctypes.data_as(_dp), N, C, H, W, f.ctypes.data_as(_dp),
-                                    FO, FI, K, m, y0, y1, out.ctypes.data_as(_dp))
+    fn = _load().oracle_forward_f64 if border == "clamp" else _load().oracle_forward_zero_f64
+    rc = fn(x.ctypes.data_as(_dp), N, C, H, W, f.ctypes.data_as(_dp), FO, FI, K, m, y0, y1,
+            out.ctypes.data_as(_dp))
     if rc != 0:
-        raise ValueError("oracle_forward_f64: invalid arguments")
+        raise ValueError("oracle forward: invalid arguments")
     return out
 
 

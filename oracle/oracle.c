@@ -98,6 +98,46 @@ int oracle_forward_f64(const double* x, int64_t N, int64_t C, int64_t H, int64_t
   return 0;
 }
 
+/*
+ * Zero border: a neighbour outside the image contributes nothing, which is
+ * what the paper's sharpen does when it skips out-of-image neighbours
+ * (Section 4.2.4).  Same loop nest as oracle_forward_f64; only the border
+ * rule differs.
+ */
+int oracle_forward_zero_f64(const double* x, int64_t N, int64_t C, int64_t H, int64_t W,
+                            const double* f, int64_t FO, int64_t FI, int64_t K, int32_t mode,
+                            int64_t y0, int64_t y1, double* out) {
+  int64_t CO = out_channels(C, FO, FI, K, mode);
+  if (CO < 0 || N < 0 || H < 0 || W < 0 || y0 < 0 || y1 < y0 || y1 > H) return -1;
+  if (N == 0 || H == 0 || W == 0 || y1 == y0) return 0;
+  int64_t r = (K - 1) / 2, rows = y1 - y0;
+  int64_t planes = N * CO;
+#pragma omp parallel for schedule(dynamic, 1)
+  for (int64_t p = 0; p < planes * rows; ++p) {
+    int64_t n = (p / rows) / CO, o = (p / rows) % CO, y = y0 + p % rows;
+    for (int64_t xx = 0; xx < W; ++xx) {
+      double acc = 0.0;
+      for (int64_t t = 0; t < n_inputs(C, mode); ++t) {
+        int64_t i, fo, fi;
+        input_of(o, t, C, FO, mode, &i, &fo, &fi);
+        const double* xi = x + (n * C + i) * H * W;
+        const double* ff = f + (fo * FI + fi) * K * K;
+        for (int64_t u = 0; u < K; ++u) {
+          int64_t sy = y + u - r;
+          if (sy < 0 || sy >= H) continue;
+          for (int64_t v = 0; v < K; ++v) {
+            int64_t sx = xx + v - r;
+            if (sx < 0 || sx >= W) continue;
+            acc += ff[u * K + v] * xi[sy * W + sx];
+          }
+        }
+      }
+      out[((n * CO + o) * rows + (y - y0)) * W + xx] = acc;
+    }
+  }
+  return 0;
+}
+
 int oracle_forward_i64(const int64_t* x, int64_t N, int64_t C, int64_t H, int64_t W,
                        const int64_t* f, int64_t FO, int64_t FI, int64_t K, int32_t mode,
                        int64_t y0, int64_t y1, int64_t* out) {

@@ -46,6 +46,11 @@ int oracle_forward_f64(const double* x, int64_t N, int64_t C, int64_t H, int64_t
                        const double* f, int64_t FO, int64_t FI, int64_t K, int32_t mode,
                        int64_t y0, int64_t y1, double* out);
 
+/* As oracle_forward_f64 with zero borders: out-of-image neighbours add 0. */
+int oracle_forward_zero_f64(const double* x, int64_t N, int64_t C, int64_t H, int64_t W,
+                            const double* f, int64_t FO, int64_t FI, int64_t K, int32_t mode,
+                            int64_t y0, int64_t y1, double* out);
+
 /* The same definition in exact int64 arithmetic (the u8 / integer-tap path). */
 int oracle_forward_i64(const int64_t* x, int64_t N, int64_t C, int64_t H, int64_t W,
                        const int64_t* f, int64_t FO, int64_t FI, int64_t K, int32_t mode,

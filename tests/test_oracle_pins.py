@@ -284,6 +284,72 @@ def test_paper_laplacian_on_parabola():
     assert not oracle.forward(np.full((h, w), 17.0), wl.LAPLACIAN_8.astype(np.float64)).any()
 
 
+# ------------------------------------------------------ pin: zero border ----
+def _scipy_zero_forward(x, f, mode):
+    """The zero-border forward map from scipy.ndimage.correlate(mode='constant',
+    cval=0): out-of-image neighbours read as 0."""
+    n_, c_, h_, w_ = x.shape
+    outs = []
+    for n in range(n_):
+        planes = []
+        if mode == "shared":
+            for c in range(c_):
+                planes.append(nd.correlate(x[n, c], f[0, 0], mode="constant", cval=0.0))
+        elif mode == "depthwise":
+            m = f.shape[0] // c_
+            for o in range(f.shape[0]):
+                planes.append(nd.correlate(x[n, o // m], f[o, 0], mode="constant", cval=0.0))
+        else:
+            for o in range(f.shape[0]):
+                planes.append(sum(nd.correlate(x[n, i], f[o, i], mode="constant", cval=0.0)
+                                  for i in range(c_)))
+        outs.append(np.stack(planes))
+    return np.stack(outs)
+
+
+@pytest.mark.parametrize("mode", ["shared", "depthwise", "bank"])
+@pytest.mark.parametrize("shape", SHAPES)
+@pytest.mark.parametrize("k", KS)
+def test_zero_border_equals_scipy_constant_correlation(mode, shape, k):
+    r = _rng(21, k, *shape)
+    x = r.random(shape)
+    f = _filter(mode, shape[1], k, r)
+    got = oracle.forward(x, f, mode, border="zero")
+    want = _scipy_zero_forward(x, f, mode)
+    assert got.shape == want.shape
+    assert np.allclose(got, want, rtol=1e-13, atol=1e-13)
+
+
+@pytest.mark.parametrize("k", [3, 5, 7])
+def test_zero_border_counts_in_image_taps_and_matches_clamp_inside(k):
+    """All-ones filter on a ones image counts the in-image taps: (r+1)^2 at a
+    corner, (r+1)(2r+1) along an edge, K^2 inside, where it also equals the
+    clamp-to-edge result of any image."""
+    rr = (k - 1) // 2
+    h, w = 3 * k, 3 * k + 2
+    y = oracle.forward(np.ones((h, w)), np.ones((k, k)), border="zero")[0, 0]
+    assert y[0, 0] == (rr + 1) ** 2 and y[-1, -1] == (rr + 1) ** 2
+    assert y[0, w // 2] == (rr + 1) * k and y[h // 2, 0] == (rr + 1) * k
+    assert y[h // 2, w // 2] == k * k
+    x = _rng(22, k).random((h, w))
+    f = _rng(23, k).standard_normal((k, k))
+    z = oracle.forward(x, f, border="zero")[0, 0]
+    c = oracle.forward(x, f)[0, 0]
+    assert np.array_equal(z[rr:h - rr, rr:w - rr], c[rr:h - rr, rr:w - rr])
+    assert not np.allclose(z[0], c[0])
+
+
+def test_zero_border_paper_laplacian_on_a_constant_image():
+    """Section 4.2.4's sharpen skips out-of-image neighbours: on a constant
+    image v the Laplacian (8 at the centre, -1 around) gives 0 inside, 8v - 5v
+    at an edge pixel (5 neighbours inside) and 8v - 3v at a corner (3 inside)."""
+    v = 10.0
+    y = oracle.forward(np.full((6, 7), v), wl.LAPLACIAN_8.astype(np.float64), border="zero")[0, 0]
+    assert np.all(y[1:-1, 1:-1] == 0.0)
+    assert y[0, 3] == 8 * v - 5 * v and y[3, 0] == 8 * v - 5 * v
+    assert y[0, 0] == 8 * v - 3 * v
+
+
 # ---------------------------------------------- pin 11: paper's grayscale ----
 def test_paper_grayscale_is_a_k1_bank():
     """Section 4.2.5: Y = 0.299 R + 0.587 G + 0.114 B, as a 3 -> 1 bank with K = 1."""
