@@ -231,6 +231,25 @@ def suite(torch, B, wl, reps):
     del xd, out, gd, gi, ws, gk, fgg
     torch.cuda.empty_cache()
 
+    # zero borders (the paper's sharpen skips out-of-image neighbours): the
+    # 3x3 Laplacian on a 3-channel 4K frame, against clamp-to-edge on the same
+    xz = torch.from_numpy(wl.sharpen_frame()).cuda()
+    lap = torch.from_numpy(wl.LAPLACIAN_8).cuda()
+    oz = torch.empty_like(xz)
+    ms_z = t.per_call_ms(lambda: B.forward(xz, lap, outs=[oz], border="zero"), reps)
+    ms_c = t.per_call_ms(lambda: B.forward(xz, lap, outs=[oz]), reps)
+    pz = xz.numel()
+    res["zero_border_f32_fwd"] = {"shape": "1x3x2160x3840 f32 (0..255), 3x3 Laplacian sharpen, zero borders",
+                                  "ms": round(ms_z, 4), "clamp_ms": round(ms_c, 4),
+                                  "mpix_taps_s": round(pz * 9 / (ms_z * 1e-3) / 1e6, 1),
+                                  "vs_plain_fwd": round(pz * 9 / (ms_z * 1e-3) / 1e6 / plain, 3),
+                                  "roofline": {"bound": "hbm",
+                                               "achieved": round(pz * 8 / (ms_z * 1e-3) / 1e9, 1),
+                                               "peak": HBM_PEAK_GBS, "unit": "GB/s",
+                                               "frac": round(pz * 8 / (ms_z * 1e-3) / 1e9 / HBM_PEAK_GBS, 4)}}
+    del xz, oz, lap
+    torch.cuda.empty_cache()
+
     # ragged batch: 64 images, H, W uniform in [256, 4096], 3 channels, 7x7 each
     sizes = wl.ragged_sizes()
     xd, yd, fdl = [], [], []

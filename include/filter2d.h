@@ -10,8 +10,9 @@
  *
  * with odd K, r = (K-1)/2, correlation (tap (u,v) weighs the neighbour at
  * offset (u-r, v-r)) and clamp-to-edge borders cl_n(t) = min(max(t,0), n-1)
- * applied to each axis.  Where the paper skips out-of-image neighbours
- * (Section 4.2.4) this library clamps; zero borders are reserved.
+ * applied to each axis.  The paper's sharpen skips out-of-image neighbours
+ * (Section 4.2.4); that rule is F2D_BORDER_ZERO (X reads as 0 outside the
+ * image), implemented for the FP32 forward.
  *
  * Channel modes (F is always a contiguous [f_out][f_in][k][k] array):
  *   F2D_CH_SHARED     f_out = f_in = 1: the same filter on every channel
@@ -66,7 +67,8 @@ typedef int32_t f2d_status;
 
 /* border rules */
 #define F2D_BORDER_CLAMP 0 /* replicate the edge pixel: cl_n(t) = min(max(t,0), n-1) */
-#define F2D_BORDER_ZERO 1  /* reserved: returns F2D_EUNSUPPORTED */
+#define F2D_BORDER_ZERO 1  /* out-of-image neighbours add nothing: FP32 filter2d_forward only
+                              (F2D_EUNSUPPORTED elsewhere) */
 
 /* channel modes */
 #define F2D_CH_SHARED 0
@@ -123,6 +125,8 @@ typedef struct f2d_opts {
  *           F32 + F32 -> F32 (all modes), FP32 accumulation;
  *           BF16 + BF16 -> F32 or BF16 (BANK only), FP32 accumulation on the
  *           matrix cores, output rounded to nearest even for BF16.
+ *   border  CLAMP for every dtype; ZERO for F32 images (all channel modes,
+ *           bands included: rows outside the buffer read as 0).
  *   K       odd, 1 <= K <= 31 (F32, U8); K in {1,3,5,7,9} for BF16 banks.
  */
 f2d_status filter2d_forward(const f2d_tensor* image, const f2d_filter* filter,

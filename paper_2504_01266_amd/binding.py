@@ -136,10 +136,14 @@ def filter_desc(f):
     return F2dFilter(f.data_ptr(), _DTYPES[f.dtype], f.size(0), f.size(1), f.size(2)), f
 
 
-def make_opts(mode="shared", epilogue=EPI_NONE, rows=None, variant=0):
+_BORDERS = {"clamp": BORDER_CLAMP, "zero": BORDER_ZERO}
+
+
+def make_opts(mode="shared", epilogue=EPI_NONE, rows=None, variant=0, border="clamp"):
     m = _MODES[mode] if isinstance(mode, str) else int(mode)
     r0, r1 = (0, 0) if rows is None else rows
-    return F2dOpts(BORDER_CLAMP, m, epilogue, variant, r0, r1)
+    b = _BORDERS[border] if isinstance(border, str) else int(border)
+    return F2dOpts(b, m, epilogue, variant, r0, r1)
 
 
 def _as4(t):
@@ -158,9 +162,10 @@ def out_count(mode, filt_shape, channels, epilogue):
 
 
 def forward(image, filt, mode="shared", epilogue=EPI_NONE, rows=None, outs=None, variant=0,
-            out_dtype=None):
+            out_dtype=None, border="clamp"):
     """Y = filter(X) on the current stream.  Returns one tensor (SHARED, BANK)
-    or the list of DEPTHWISE outputs (one per filter index, plus the SUMSQ one)."""
+    or the list of DEPTHWISE outputs (one per filter index, plus the SUMSQ one).
+    border: "clamp" (clamp-to-edge) or "zero" (FP32 images)."""
     lib = load()
     image = _as4(image)
     fd, filt = filter_desc(filt)
@@ -177,7 +182,7 @@ def forward(image, filt, mode="shared", epilogue=EPI_NONE, rows=None, outs=None,
         outs = [torch.empty((n, co, r1 - r0, w), dtype=odt, device=image.device)
                 for _ in range(nout)]
     descs = (F2dTensor * len(outs))(*[tensor_desc(o) for o in outs])
-    opts = make_opts(m, epilogue, (r0, r1), variant)
+    opts = make_opts(m, epilogue, (r0, r1), variant, border)
     _check(lib.filter2d_forward(ctypes.byref(tensor_desc(image)), ctypes.byref(fd),
                                 ctypes.byref(opts), descs, len(outs), _stream()))
     return outs if m == DEPTHWISE else outs[0]

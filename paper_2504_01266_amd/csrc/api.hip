@@ -171,9 +171,8 @@ f2d_status check_common(const f2d_tensor* image, const f2d_filter* filter, const
   if (!filter) return fail(F2D_EINVAL, "filter is NULL");
   f2d_status s = check_tensor(image, "image", false);
   if (s) return s;
-  if (opts->border == F2D_BORDER_ZERO)
-    return fail(F2D_EUNSUPPORTED, "border F2D_BORDER_ZERO is reserved; only clamp-to-edge is implemented");
-  if (opts->border != F2D_BORDER_CLAMP) return fail(F2D_EINVAL, "unknown border %d", opts->border);
+  if (opts->border != F2D_BORDER_CLAMP && opts->border != F2D_BORDER_ZERO)
+    return fail(F2D_EINVAL, "unknown border %d", opts->border);
   if (opts->channels < F2D_CH_SHARED || opts->channels > F2D_CH_BANK)
     return fail(F2D_EINVAL, "unknown channel mode %d", opts->channels);
   if (opts->epilogue != F2D_EPI_NONE && opts->epilogue != F2D_EPI_SUMSQ_PAIRS)
@@ -240,6 +239,8 @@ f2d_status check_common(const f2d_tensor* image, const f2d_filter* filter, const
   } else {
     return fail(F2D_EUNSUPPORTED, "image dtype %d is not supported", it);
   }
+  if (opts->border == F2D_BORDER_ZERO && it != F2D_F32)
+    return fail(F2D_EUNSUPPORTED, "zero borders are implemented for f32 images only");
   pr->image = *image;
   pr->filter = *filter;
   pr->opts = *opts;
@@ -299,6 +300,7 @@ f2d_status filter2d_forward_separable(const f2d_tensor* image, const float* a, c
   f2d_status s = check_common(image, &filter, opts, &pr);
   if (s) return s;
   if (image->dtype != F2D_F32) return fail(F2D_EUNSUPPORTED, "separable: f32 images only");
+  if (opts->border != F2D_BORDER_CLAMP) return fail(F2D_EUNSUPPORTED, "separable: clamp-to-edge borders only");
   if (k > 15) return fail(F2D_EUNSUPPORTED, "separable: k=%d (1..15 are built)", k);
   s = check_outputs(pr, out, 1, "out");
   if (s) return s;
@@ -309,6 +311,7 @@ size_t filter2d_backward_workspace(const f2d_tensor* image, const f2d_filter* fi
                                    const f2d_opts* opts) {
   Problem pr;
   if (check_common(image, filter, opts, &pr)) return 0;
+  if (opts->border != F2D_BORDER_CLAMP) return 0;
   return backward_workspace(pr);
 }
 
@@ -319,6 +322,8 @@ f2d_status filter2d_backward(const f2d_tensor* image, const f2d_filter* filter,
   Problem pr;
   f2d_status s = check_common(image, filter, opts, &pr);
   if (s) return s;
+  if (opts->border != F2D_BORDER_CLAMP)
+    return fail(F2D_EUNSUPPORTED, "backward: clamp-to-edge borders only (zero borders are forward-only)");
   return run_backward(pr, grad_outs, n_grad_outs, grad_input, grad_filter, workspace, workspace_bytes,
                       static_cast<hipStream_t>(stream));
 }

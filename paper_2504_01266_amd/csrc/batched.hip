@@ -188,7 +188,8 @@ f2d_status run_batched(const f2d_batch_item* items_dev, const int64_t* tile_pref
                        int64_t total_tiles, int32_t dtype, int32_t k, const f2d_opts* opts,
                        hipStream_t s) {
   if (!opts) return fail(F2D_EINVAL, "opts is NULL");
-  if (opts->border == F2D_BORDER_ZERO) return fail(F2D_EUNSUPPORTED, "border F2D_BORDER_ZERO is reserved");
+  if (opts->border == F2D_BORDER_ZERO)
+    return fail(F2D_EUNSUPPORTED, "ragged batch: clamp-to-edge borders only");
   if (opts->border != F2D_BORDER_CLAMP) return fail(F2D_EINVAL, "unknown border %d", opts->border);
   if (opts->channels != F2D_CH_SHARED) return fail(F2D_EUNSUPPORTED, "batched: SHARED mode only");
   if (k < 1 || k > 31 || k % 2 == 0) return fail(F2D_EINVAL, "k=%d: must be odd, 1..31", k);

@@ -56,7 +56,56 @@ bool all_aligned(const f2d_tensor* outs, int32_t n, size_t bytes) {
 constexpr int kMaxTemplK = 9;    // templated f32 kernels exist for K <= 9
 constexpr int kMaxTaps = 100;    // NOUT*K*K limit of the templated kernels
 
+// Zero borders (out-of-image neighbours add nothing, as in the paper's
+// sharpen): one output plane per work-group tile with zero-border staging,
+// the 64 x 64 templated kernel for K <= 9 and the runtime-K kernel above
+// (DEPTHWISE: one launch per filter index).
+f2d_status forward_f32_zero(const Problem& pr, const f2d_tensor* outs, hipStream_t s) {
+  const int variant = pr.k <= kMaxTemplK ? 1 : -1;
+  const TileShape tg = f32_tile(variant);
+  const int64_t C = pr.image.c;
+  const int32_t vecflag = all_aligned(outs, pr.mode == F2D_CH_DEPTHWISE ? pr.m : 1, 16) ? kDstVec : 0;
+  auto go = [&](StencilParams& p) -> f2d_status {
+    p.flags = kZeroBorder | vecflag;
+    if (f2d_status e = size_grid(p, pr.image.n, tg)) return e;
+    return hip_status(launch_stencil_f32(p, pr.k, 1, false, variant, s), "forward f32 zero-border launch");
+  };
+  if (pr.mode == F2D_CH_SHARED) {
+    StencilParams p = base_params(pr);
+    set_dst(p, 0, outs[0]);
+    p.groups = static_cast<int32_t>(C);
+    p.nsrc = 1;
+    p.sc_g = 1;
+    p.dc_g = 1;
+    return go(p);
+  }
+  if (pr.mode == F2D_CH_DEPTHWISE) {
+    for (int j = 0; j < pr.m; ++j) {
+      StencilParams p = base_params(pr);
+      set_dst(p, 0, outs[j]);
+      p.groups = static_cast<int32_t>(C);
+      p.nsrc = 1;
+      p.sc_g = 1;
+      p.dc_g = 1;
+      p.f0 = j;
+      p.fg = pr.m;
+      if (f2d_status e = go(p)) return e;
+    }
+    return ok();
+  }
+  StencilParams p = base_params(pr);  // BANK: output channel g sums all C sources
+  set_dst(p, 0, outs[0]);
+  p.groups = static_cast<int32_t>(pr.c_out);
+  p.nsrc = static_cast<int32_t>(C);
+  p.sc_s = 1;
+  p.dc_g = 1;
+  p.fg = static_cast<int32_t>(C);
+  p.fs = 1;
+  return go(p);
+}
+
 f2d_status forward_f32(const Problem& pr, const f2d_tensor* outs, int32_t n_outs, hipStream_t s) {
+  if (pr.opts.border == F2D_BORDER_ZERO) return forward_f32_zero(pr, outs, s);
   const int K = pr.k;
   const bool templ = K <= kMaxTemplK;
   const int variant =

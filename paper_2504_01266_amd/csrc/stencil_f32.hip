@@ -89,7 +89,8 @@ __device__ __forceinline__ void store_adjoint(const StencilParams& p, int64_t n,
 
 // MT: sources come from several tensors (the depthwise adjoint reads the m
 // upstream gradients); otherwise every source plane is in src[0].
-template <int K, int NOUT, bool ADJ, bool MT, int PX, int PY>
+// ZB: forward map with zero borders (out-of-image neighbours read as 0).
+template <int K, int NOUT, bool ADJ, bool MT, int PX, int PY, bool ZB = false>
 __global__ __launch_bounds__(kThreads) void k_stencil_f32(StencilParams p) {
   using G = Geom<K, PX, PY>;
   __shared__ float4 lds4[(G::LDS_WORDS + 3) / 4];
@@ -125,7 +126,7 @@ __global__ __launch_bounds__(kThreads) void k_stencil_f32(StencilParams p) {
       sp = static_cast<const float*>(p.src[0]) + n * p.src_sn[0] + ch * p.src_sc[0];
       sh = p.src_sh[0];
     }
-    stage_tile<K, PX, PY, ADJ, NOUT == 1>(lds, sp, sh, p.H, p.W, p.row0 + oy0, ox0);
+    stage_tile<K, PX, PY, ADJ || ZB, NOUT == 1>(lds, sp, sh, p.H, p.W, p.row0 + oy0, ox0);
 
     float tap[NOUT][K * K];
 #pragma unroll
@@ -209,6 +210,14 @@ hipError_t go(const StencilParams& p, hipStream_t stream) {
   return hipGetLastError();
 }
 
+// zero-border forward: one output plane per tile, 64 x 64 tiles
+template <int K>
+hipError_t go_zero(const StencilParams& p, hipStream_t stream) {
+  hipLaunchKernelGGL((k_stencil_f32<K, 1, false, false, 4, 4, true>), dim3(static_cast<uint32_t>(p.n_blocks)),
+                     dim3(kThreads), 0, stream, p);
+  return hipGetLastError();
+}
+
 template <int K, int NOUT, bool ADJ>
 hipError_t by_variant(const StencilParams& p, int variant, hipStream_t stream) {
   if constexpr (NOUT == 1 && !ADJ) {
@@ -265,6 +274,17 @@ hipError_t launch_stencil_f32(const StencilParams& p, int K, int nout, bool adjo
     hipLaunchKernelGGL(k_stencil_f32_generic, dim3(static_cast<uint32_t>(p.n_blocks)),
                        dim3(kThreads), 0, stream, p);
     return hipGetLastError();
+  }
+  if (p.flags & kZeroBorder) {  // forward with zero borders (variant 1 tiling)
+    if (nout != 1 || adjoint) return hipErrorInvalidValue;
+    switch (K) {
+      case 1: return go_zero<1>(p, stream);
+      case 3: return go_zero<3>(p, stream);
+      case 5: return go_zero<5>(p, stream);
+      case 7: return go_zero<7>(p, stream);
+      case 9: return go_zero<9>(p, stream);
+      default: return hipErrorInvalidValue;
+    }
   }
   switch (K) {
     case 1: return by_nout<1>(p, nout, adjoint, variant, stream);

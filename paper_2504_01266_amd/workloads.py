@@ -123,6 +123,12 @@ def ragged_item(i, h, w, c=3, k=7):
     return x, f.astype(np.float32)
 
 
+def sharpen_frame(h=2160, w=3840, c=3):
+    """A 4K 3-channel frame with integer values 0..255 stored as float32 (the
+    sharpen of Section 4.2.4 on an 8-bit image, in the FP32 path)."""
+    return rng(9, 4, h, w).integers(0, 256, (1, c, h, w)).astype(np.float32)
+
+
 def diff_image(n, c=3, h=2048, w=2048):
     return rng(DIFF_SEED, 1, n).random((c, h, w), dtype=np.float32)
 

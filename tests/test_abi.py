@@ -78,8 +78,8 @@ CASES = [
      [_img()], B.EINVAL, "multiple"),
     ("bank f_in != C", _img(c=3), _filt(f_out=4, f_in=2), B.make_opts("bank"), [_img()], B.EINVAL,
      "f_in"),
-    ("zero border reserved", _img(), _filt(), B.F2dOpts(B.BORDER_ZERO, 0, 0, 0, 0, 0), [_img()],
-     B.EUNSUPPORTED, "reserved"),
+    ("zero border on u8", _img(B.U8), _filt(dtype=B.I32), B.F2dOpts(B.BORDER_ZERO, 0, 0, 0, 0, 0),
+     [_img(B.I32)], B.EUNSUPPORTED, "f32 images only"),
     ("unknown border", _img(), _filt(), B.F2dOpts(7, 0, 0, 0, 0, 0), [_img()], B.EINVAL, "border"),
     ("wrong output count", _img(), _filt(), B.make_opts(), [_img(), _img()], B.EINVAL, "expected 1"),
     ("wrong output shape", _img(), _filt(), B.make_opts(), [_img(h=31)], B.EINVAL, "shape"),
@@ -120,6 +120,7 @@ SEP_CASES = [
     ("wrong output shape", _img(), FAKE, 3, B.make_opts(), _img(w=39), B.EINVAL, "shape"),
     ("band outside image", _img(h=32), FAKE, 3, B.make_opts(rows=(10, 40)), _img(h=30), B.EINVAL,
      "outside"),
+    ("zero border", _img(), FAKE, 3, B.make_opts(border="zero"), _img(), B.EUNSUPPORTED, "clamp"),
 ]
 
 
@@ -144,6 +145,12 @@ def test_backward_validation_on_the_host(lib):
     st = lib.filter2d_backward(ctypes.byref(image), ctypes.byref(filt), g, 1,
                                ctypes.byref(B.make_opts(rows=(0, 8))), None, None, None, 0, None)
     assert st == B.EUNSUPPORTED
+    # zero borders are forward-only
+    zopts = B.make_opts(border="zero")
+    st = lib.filter2d_backward(ctypes.byref(image), ctypes.byref(filt), g, 1,
+                               ctypes.byref(zopts), None, None, None, 0, None)
+    assert st == B.EUNSUPPORTED and "zero" in B.last_error().lower()
+    assert lib.filter2d_backward_workspace(ctypes.byref(image), ctypes.byref(filt), ctypes.byref(zopts)) == 0
     # even K
     st = lib.filter2d_backward(ctypes.byref(image), ctypes.byref(_filt(k=2)), g, 1,
                                ctypes.byref(opts), None, None, None, 0, None)
