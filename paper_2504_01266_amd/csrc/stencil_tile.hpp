@@ -113,27 +113,25 @@ __device__ __forceinline__ void stage_tile(float* __restrict__ lds, const float*
       coff[j] = static_cast<uint32_t>(gx < 0 ? 0 : (gx >= W ? W - 1 : gx));
     }
   }
+  // Every load is unconditional (the addresses are always valid); the zero
+  // mask is applied only when writing LDS, so the compiler cannot turn the
+  // masked values into branches around the loads, each followed by a wait.
   float buf[RPW][CPL];
+  bool rval[RPW];
 #pragma unroll
   for (int i = 0; i < RPW; ++i) {
     const int ly = wave + kWaves * i;
     int64_t gy = row_base - G::R + (ly < G::LH ? ly : G::LH - 1);
-    bool rval = true;
+    rval[i] = true;
     if constexpr (ADJ) {
-      rval = gy >= 0 && gy < H;
-      gy = rval ? gy : 0;
+      rval[i] = gy >= 0 && gy < H;
+      gy = rval[i] ? gy : 0;
     } else {
       gy = gy < 0 ? 0 : (gy >= H ? H - 1 : gy);
     }
     const float* rp = sp + gy * sh;
 #pragma unroll
-    for (int j = 0; j < CPL; ++j) {
-      const float v = rp[coff[j]];
-      if constexpr (ADJ)
-        buf[i][j] = (rval && cval[j]) ? v : 0.0f;
-      else
-        buf[i][j] = v;
-    }
+    for (int j = 0; j < CPL; ++j) buf[i][j] = rp[coff[j]];
   }
 #pragma unroll
   for (int i = 0; i < RPW; ++i) {
@@ -141,7 +139,9 @@ __device__ __forceinline__ void stage_tile(float* __restrict__ lds, const float*
 #pragma unroll
     for (int j = 0; j < CPL; ++j) {
       const int lx = lane + kWaveLanes * j;
-      if (ly < G::LH && lx < G::LW) lds[ly * G::PITCH + lx] = buf[i][j];
+      float v = buf[i][j];
+      if constexpr (ADJ) v = (rval[i] && cval[j]) ? v : 0.0f;
+      if (ly < G::LH && lx < G::LW) lds[ly * G::PITCH + lx] = v;
     }
   }
 }
