@@ -113,35 +113,49 @@ __device__ __forceinline__ void stage_tile(float* __restrict__ lds, const float*
       coff[j] = static_cast<uint32_t>(gx < 0 ? 0 : (gx >= W ? W - 1 : gx));
     }
   }
-  // Every load is unconditional (the addresses are always valid); the zero
-  // mask is applied only when writing LDS, so the compiler cannot turn the
-  // masked values into branches around the loads, each followed by a wait.
   float buf[RPW][CPL];
-  bool rval[RPW];
+  if constexpr (ADJ) {
+    // Every load is unconditional (the addresses are always valid) and the
+    // zero mask is applied at the LDS write: masking each loaded value had
+    // the compiler branch around each load and wait for it in turn.
+    bool rval[RPW];
 #pragma unroll
-  for (int i = 0; i < RPW; ++i) {
-    const int ly = wave + kWaves * i;
-    int64_t gy = row_base - G::R + (ly < G::LH ? ly : G::LH - 1);
-    rval[i] = true;
-    if constexpr (ADJ) {
+    for (int i = 0; i < RPW; ++i) {
+      const int ly = wave + kWaves * i;
+      const int64_t gy = row_base - G::R + (ly < G::LH ? ly : G::LH - 1);
       rval[i] = gy >= 0 && gy < H;
-      gy = rval[i] ? gy : 0;
-    } else {
-      gy = gy < 0 ? 0 : (gy >= H ? H - 1 : gy);
+      const float* rp = sp + (rval[i] ? gy : 0) * sh;
+#pragma unroll
+      for (int j = 0; j < CPL; ++j) buf[i][j] = rp[coff[j]];
     }
-    const float* rp = sp + gy * sh;
 #pragma unroll
-    for (int j = 0; j < CPL; ++j) buf[i][j] = rp[coff[j]];
-  }
+    for (int i = 0; i < RPW; ++i) {
+      const int ly = wave + kWaves * i;
 #pragma unroll
-  for (int i = 0; i < RPW; ++i) {
-    const int ly = wave + kWaves * i;
+      for (int j = 0; j < CPL; ++j) {
+        const int lx = lane + kWaveLanes * j;
+        const float v = (rval[i] && cval[j]) ? buf[i][j] : 0.0f;
+        if (ly < G::LH && lx < G::LW) lds[ly * G::PITCH + lx] = v;
+      }
+    }
+  } else {
 #pragma unroll
-    for (int j = 0; j < CPL; ++j) {
-      const int lx = lane + kWaveLanes * j;
-      float v = buf[i][j];
-      if constexpr (ADJ) v = (rval[i] && cval[j]) ? v : 0.0f;
-      if (ly < G::LH && lx < G::LW) lds[ly * G::PITCH + lx] = v;
+    for (int i = 0; i < RPW; ++i) {
+      const int ly = wave + kWaves * i;
+      int64_t gy = row_base - G::R + (ly < G::LH ? ly : G::LH - 1);
+      gy = gy < 0 ? 0 : (gy >= H ? H - 1 : gy);
+      const float* rp = sp + gy * sh;
+#pragma unroll
+      for (int j = 0; j < CPL; ++j) buf[i][j] = rp[coff[j]];
+    }
+#pragma unroll
+    for (int i = 0; i < RPW; ++i) {
+      const int ly = wave + kWaves * i;
+#pragma unroll
+      for (int j = 0; j < CPL; ++j) {
+        const int lx = lane + kWaveLanes * j;
+        if (ly < G::LH && lx < G::LW) lds[ly * G::PITCH + lx] = buf[i][j];
+      }
     }
   }
 }
