@@ -78,3 +78,17 @@ def test_zero_border_identity_is_bitwise(gpu_lib, k):
     f[k // 2, k // 2] = 1.0
     y = gpu_lib.forward(dev(x), dev(f), border="zero")
     assert torch.equal(y.cpu(), torch.from_numpy(x))
+
+
+@pytest.mark.slow
+def test_zero_border_full_size_sharpen(gpu_lib):
+    """The benchmark's launch: 3-channel 4K frame (0..255), 3x3 Laplacian with
+    zero borders; row bands at the top, the middle and the bottom against the
+    oracle, bit-exact (integer data and taps)."""
+    x = wl.sharpen_frame()
+    f = wl.LAPLACIAN_8
+    y = gpu_lib.forward(dev(x), dev(f), border="zero")
+    torch.cuda.synchronize()
+    for r0, r1 in [(0, 6), (1077, 1083), (2154, 2160)]:
+        ref = oracle.forward(x, f.astype(np.float64), rows=(r0, r1), border="zero")
+        assert np.array_equal(y[:, :, r0:r1].double().cpu().numpy(), ref)
