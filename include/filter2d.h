@@ -67,7 +67,8 @@ typedef int32_t f2d_status;
 
 /* border rules */
 #define F2D_BORDER_CLAMP 0 /* replicate the edge pixel: cl_n(t) = min(max(t,0), n-1) */
-#define F2D_BORDER_ZERO 1  /* out-of-image neighbours add nothing: FP32 filter2d_forward only
+#define F2D_BORDER_ZERO 1  /* out-of-image neighbours add nothing (the paper's sharpen,
+                              Section 4.2.4): FP32 filter2d_forward only
                               (F2D_EUNSUPPORTED elsewhere) */
 
 /* channel modes */
@@ -127,7 +128,9 @@ typedef struct f2d_opts {
  *           matrix cores, output rounded to nearest even for BF16.
  *   border  CLAMP for every dtype; ZERO for F32 images (all channel modes,
  *           bands included: rows outside the buffer read as 0).
- *   K       odd, 1 <= K <= 31 (F32, U8); K in {1,3,5,7,9} for BF16 banks.
+ *   K       odd, 1 <= K <= 31 (F32, U8); K in {1,3,5} for BF16 banks (other
+ *           odd K return F2D_EUNSUPPORTED); BF16 banks take at most 64 input
+ *           channels.
  */
 f2d_status filter2d_forward(const f2d_tensor* image, const f2d_filter* filter,
                             const f2d_opts* opts, const f2d_tensor* outs, int32_t n_outs,
@@ -159,14 +162,20 @@ f2d_status filter2d_forward_separable(const f2d_tensor* image, const float* a, c
 /*
  * Workspace bytes that filter2d_backward needs for these arguments (device
  * memory, caller-allocated, any alignment >= 256 bytes).  Returns 0 for
- * invalid arguments.
+ * invalid arguments.  The workspace holds the r-wide frame of the image
+ * adjoint (folded onto the edge pixels afterwards) and the per-work-unit
+ * grad_filter partial sums of the reduction below; the paper's own
+ * reductions (Section 4.2.8) combine per-block partials the same way.
  */
 size_t filter2d_backward_workspace(const f2d_tensor* image, const f2d_filter* filter,
                                    const f2d_opts* opts);
 
 /*
  * filter2d_backward -- the adjoints of filter2d_forward (whole images only:
- * opts->row_begin/row_end must select all rows).
+ * opts->row_begin/row_end must select all rows).  The paper defines only the
+ * forward weighted sum (Section 4.2.4); these are the transposes of that
+ * linear map, in the image and in the filter, which gradient-based callers
+ * (training a filter bank) need.
  *
  *   grad_outs    n_grad_outs upstream gradients laid out like forward's outs
  *                (no SUMSQ output); F32 (or BF16 for BF16 banks).
@@ -189,9 +198,9 @@ f2d_status filter2d_backward(const f2d_tensor* image, const f2d_filter* filter,
 
 /*
  * Ragged batches: images of different sizes, each with its own filter,
- * filtered in ONE persistent launch (the batch processing the paper lists as
- * missing in Section 5).  SHARED mode, F32, clamp-to-edge; every item uses
- * the same K.
+ * filtered in ONE launch (the batch processing the paper lists as missing in
+ * Section 5).  SHARED mode, F32, clamp-to-edge; every item uses the same K
+ * (odd, 1..9).
  */
 typedef struct f2d_batch_item {
   const void* image;  /* device [c][h][w] */
@@ -202,20 +211,26 @@ typedef struct f2d_batch_item {
 } f2d_batch_item;
 
 /*
- * Host-side plan: validates the items (host copies) and writes the tile prefix
- * sum tile_prefix[0..n_items] (host array).  *variant selects the tiling
- * (0 = tuned / default, replaced by the resolved variant on return); pass the
- * same variant in opts->variant to filter2d_batched.  Returns the total
- * number of tiles, or a negative f2d_status on error.
+ * Host-side plan: validates the items (host copies) and writes n_items + 2
+ * words to tile_prefix (host array): the tile prefix sum tile_prefix[0..n_items]
+ * followed by a tag that records the resolved variant and k.  *variant
+ * selects the tiling (0 = tuned / default, replaced by the resolved variant
+ * on return); pass the same variant and k to filter2d_batched.  Returns the
+ * total number of tiles, or a negative f2d_status on error.
  */
 int64_t filter2d_batched_plan(const f2d_batch_item* items, int32_t n_items, int32_t dtype,
                               int32_t k, int32_t* variant, int64_t* tile_prefix);
 
 /*
- * filter2d_batched -- one persistent launch over every tile of every item.
- * items_dev and tile_prefix_dev are device copies of the plan's inputs and
- * outputs.  The call reads nothing from them on the host, so it is safe to
- * capture into a hipGraph and replay while the tables stay resident.
+ * filter2d_batched -- one launch over every tile of every item, one
+ * work-group per tile (each finds its item in the prefix table).
+ * items_dev and tile_prefix_dev (n_items + 2 words) are device copies of the
+ * plan's inputs and outputs.  The call reads nothing from them on the host,
+ * so it is safe to capture into a hipGraph and replay while the tables stay
+ * resident.  The kernel compares the table's tag with opts->variant and k: a
+ * table planned for another variant or k is detected on the device and the
+ * launch then writes nothing (the host cannot see the device table, so the
+ * call still returns F2D_OK).
  */
 f2d_status filter2d_batched(const f2d_batch_item* items_dev, const int64_t* tile_prefix_dev,
                             int32_t n_items, int64_t total_tiles, int32_t dtype, int32_t k,
@@ -247,8 +262,15 @@ f2d_status filter2d_tune_load(const char* path);
 /* Drop every tuned entry (variant 0 then means the built-in default). */
 void filter2d_tune_clear(void);
 
+/*
+ * Error reporting.  The paper lists inconsistent and limited error handling
+ * as a shortcoming of its API (Section 5); here every entry point returns a
+ * status and keeps a message.  filter2d_status_string: a static description
+ * of a status code.  filter2d_last_error: the detail of the last non-OK
+ * status returned on this thread (host string, valid until the thread's next
+ * call into the library).
+ */
 const char* filter2d_status_string(f2d_status s);
-/* Detail of the last non-OK status returned on this thread (host string). */
 const char* filter2d_last_error(void);
 /* Library version as major*10000 + minor*100 + patch. */
 int32_t filter2d_version(void);

@@ -218,9 +218,10 @@ def backward_workspace(image, filt, mode="shared"):
 
 
 def backward(image, filt, grad_outs, mode="shared", need_input=True, need_filter=True,
-             workspace=None):
+             workspace=None, grad_input=None, grad_filter=None):
     """Adjoints of ``forward``: returns (grad_input [N][C][H][W] f32 or None,
-    grad_filter f32 shaped like the filter or None)."""
+    grad_filter f32 shaped like the filter or None).  grad_input / grad_filter
+    may be given as preallocated outputs."""
     lib = load()
     image = _as4(image)
     fd, filt4 = filter_desc(filt)
@@ -228,8 +229,15 @@ def backward(image, filt, grad_outs, mode="shared", need_input=True, need_filter
         grad_outs = [grad_outs]
     grad_outs = [_as4(g) for g in grad_outs]
     opts = make_opts(mode)
-    gi = torch.empty(image.shape, dtype=torch.float32, device=image.device) if need_input else None
-    gf = torch.empty(filt4.shape, dtype=torch.float32, device=image.device) if need_filter else None
+    gi, gf = None, None
+    if need_input:
+        gi = grad_input if grad_input is not None else \
+            torch.empty(image.shape, dtype=torch.float32, device=image.device)
+    if need_filter:
+        gf = grad_filter if grad_filter is not None else \
+            torch.empty(filt4.shape, dtype=torch.float32, device=image.device)
+        if gf.numel() != filt4.numel() or gf.dtype != torch.float32 or not gf.is_contiguous():
+            raise ValueError("grad_filter must be a contiguous float32 tensor with the filter's size")
     ws_bytes = lib.filter2d_backward_workspace(ctypes.byref(tensor_desc(image)), ctypes.byref(fd),
                                                ctypes.byref(opts))
     if workspace is None or workspace.numel() < ws_bytes:
@@ -282,7 +290,8 @@ def tune_clear():
 
 
 class RaggedBatch:
-    """Descriptor table + tile plan for ``filter2d_batched``, resident on the device.
+    """Descriptor table + tile plan (prefix sums and tag) for ``filter2d_batched``,
+    resident on the device.
 
     images / outs: lists of [C][H][W] tensors (float32, column stride 1);
     filters: list of [K][K] float32 tensors (one per image)."""
@@ -302,7 +311,7 @@ class RaggedBatch:
                                     x.size(2), x.stride(0), x.stride(1), y.stride(0), y.stride(1))
         self.items_host = items
         self.n = n
-        prefix = (ctypes.c_int64 * (n + 1))()
+        prefix = (ctypes.c_int64 * (n + 2))()  # prefix sums + the plan's tag word
         var = ctypes.c_int32(variant)
         total = lib.filter2d_batched_plan(items, n, F32, self.k, ctypes.byref(var), prefix)
         if total < 0:
@@ -313,15 +322,18 @@ class RaggedBatch:
         raw = bytes(memoryview(items)) if n else b""
         self.items_dev = torch.frombuffer(bytearray(raw), dtype=torch.uint8).to(dev) if n else \
             torch.empty(1, dtype=torch.uint8, device=dev)
-        self.prefix_host = [prefix[i] for i in range(n + 1)]
+        self.prefix_host = [prefix[i] for i in range(n + 2)]
         self.prefix_dev = torch.tensor(self.prefix_host, dtype=torch.int64, device=dev)
 
-    def run(self):
+    def run(self, variant=None, k=None):
+        """Launch on the current stream.  variant / k default to the planned
+        ones (others are only for testing the device-side plan check)."""
         lib = load()
-        opts = make_opts("shared", variant=self.variant)
+        opts = make_opts("shared", variant=self.variant if variant is None else variant)
         _check(lib.filter2d_batched(ctypes.c_void_p(self.items_dev.data_ptr()),
                                     ctypes.c_void_p(self.prefix_dev.data_ptr()), self.n,
-                                    self.total_tiles, F32, self.k, ctypes.byref(opts), _stream()))
+                                    self.total_tiles, F32, self.k if k is None else k,
+                                    ctypes.byref(opts), _stream()))
 
     def autotune(self, reps=3):
         lib = load()

@@ -234,7 +234,7 @@ f2d_status check_common(const f2d_tensor* image, const f2d_filter* filter, const
   } else if (it == F2D_BF16) {
     if (ft != F2D_BF16) return fail(F2D_EINVAL, "bf16 images need a bf16 filter");
     if (opts->channels != F2D_CH_BANK) return fail(F2D_EUNSUPPORTED, "bf16 images: only BANK mode is implemented");
-    if (k > 9) return fail(F2D_EUNSUPPORTED, "bf16 banks: k must be <= 9");
+    if (k != 1 && k != 3 && k != 5) return fail(F2D_EUNSUPPORTED, "bf16 banks: k in {1, 3, 5} (got %d)", k);
     pr->out_dtype = F2D_F32;  // or BF16, chosen by the output descriptor
   } else {
     return fail(F2D_EUNSUPPORTED, "image dtype %d is not supported", it);

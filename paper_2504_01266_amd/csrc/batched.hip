@@ -1,12 +1,16 @@
-// Ragged batch: every tile of every image of a batch in ONE persistent launch.
+// Ragged batch: every tile of every image of a batch in ONE launch.
 //
 // The host plan turns the items (images of different sizes, each with its own
-// K x K filter) into a prefix sum of per-item tile counts.  The kernel runs
-// one work-group per tile of the global tile list; a work-group finds the
-// owning item by binary search in the prefix table and runs the same tile
-// code as the single-image FP32 path (SHARED mode, clamp-to-edge).  The grid
-// comes from the plan's tile count and nothing is read on the host at launch
-// time, so the call can be captured in a hipGraph and replayed.
+// K x K filter) into a prefix sum of per-item tile counts, followed by a tag
+// that records the tiling variant and K it was planned for.  The kernel runs
+// one work-group per tile of the global tile list (the hardware starts the
+// next work-group as soon as one retires); a work-group finds the owning item
+// by binary search in the prefix table and runs the same tile code as the
+// single-image FP32 path (SHARED mode, clamp-to-edge).  A table planned for
+// another variant or K is recognised on the device from its tag and the
+// launch then writes nothing.  The grid comes from the plan's tile count and
+// nothing is read on the host at launch time, so the call can be captured in
+// a hipGraph and replayed.
 #include <hip/hip_runtime.h>
 
 #include <cstring>
@@ -21,11 +25,20 @@ namespace {
 
 using namespace tile;
 
+// Tag word after the prefix sums: the plan's variant and K.
+constexpr int64_t kPlanMagic = int64_t{0x46324442} << 32;  // "F2DB"
+__host__ __device__ inline int64_t plan_tag(int variant, int k) {
+  return kPlanMagic | (static_cast<int64_t>(k) << 8) | static_cast<int64_t>(variant);
+}
+
 template <int K, int PX, int PY>
 __global__ __launch_bounds__(kThreads) void k_batched_f32(const f2d_batch_item* __restrict__ items,
                                                           const int64_t* __restrict__ prefix,
-                                                          int32_t n_items, int64_t total_tiles) {
+                                                          int32_t n_items, int64_t total_tiles,
+                                                          int64_t tag) {
   using G = Geom<K, PX, PY>;
+  // a table planned for another tile shape or K: write nothing (uniform)
+  if (prefix[n_items + 1] != tag) return;
   __shared__ float4 lds4[(G::LDS_WORDS + 3) / 4];
   float* lds = reinterpret_cast<float*>(lds4);
   const int tx = threadIdx.x % kTX;
@@ -72,6 +85,7 @@ __global__ __launch_bounds__(kThreads) void k_batched_f32(const f2d_batch_item* 
     }
     const uint32_t local = static_cast<uint32_t>(t - start);
     const uint32_t c = local / per_plane;
+    if (c >= it.c) continue;  // uniform; unreachable with a matching plan
     const uint32_t r = local - c * per_plane;
     const uint32_t tile_y = r / tiles_x;
     const uint32_t tile_x = r - tile_y * tiles_x;
@@ -109,23 +123,24 @@ struct Shape {
 // staging overlaps other tiles' arithmetic; measured faster than a grid that
 // only fills the device once.
 template <int K, int PX, int PY>
-hipError_t launch(const f2d_batch_item* items, const int64_t* prefix, int32_t n, int64_t total,
+hipError_t launch(const f2d_batch_item* items, const int64_t* prefix, int32_t n, int64_t total, int64_t tag,
                   hipStream_t s) {
   constexpr int64_t kMaxGrid = int64_t{1} << 30;
   const int64_t g = total < kMaxGrid ? total : kMaxGrid;
   hipLaunchKernelGGL((k_batched_f32<K, PX, PY>), dim3(static_cast<uint32_t>(g)), dim3(kThreads), 0, s,
-                     items, prefix, n, total);
+                     items, prefix, n, total, tag);
   return hipGetLastError();
 }
 
 template <int K>
 hipError_t by_variant(int variant, const f2d_batch_item* items, const int64_t* prefix, int32_t n,
                       int64_t total, hipStream_t s) {
+  const int64_t tag = plan_tag(variant, K);
   switch (variant) {
-    case 2: return launch<K, 4, 2>(items, prefix, n, total, s);
-    case 3: return launch<K, 4, 8>(items, prefix, n, total, s);
-    case 4: return launch<K, 8, 2>(items, prefix, n, total, s);
-    default: return launch<K, 4, 4>(items, prefix, n, total, s);
+    case 2: return launch<K, 4, 2>(items, prefix, n, total, tag, s);
+    case 3: return launch<K, 4, 8>(items, prefix, n, total, tag, s);
+    case 4: return launch<K, 8, 2>(items, prefix, n, total, tag, s);
+    default: return launch<K, 4, 4>(items, prefix, n, total, tag, s);
   }
 }
 
@@ -179,6 +194,7 @@ int64_t batched_plan(const f2d_batch_item* items, int32_t n_items, int32_t dtype
     const int64_t tiles = it.c * ((it.h + ts.th - 1) / ts.th) * ((it.w + ts.tw - 1) / ts.tw);
     tile_prefix[i + 1] = tile_prefix[i] + tiles;
   }
+  tile_prefix[n_items + 1] = plan_tag(v, k);
   *variant = v;
   ok();
   return tile_prefix[n_items];
@@ -217,7 +233,7 @@ f2d_status autotune_batched(const f2d_batch_item* items_host, const f2d_batch_it
                             int32_t reps, hipStream_t s, int32_t* best) {
   if (reps < 1) return fail(F2D_EINVAL, "autotune: reps must be >= 1");
   if (!tile_prefix_dev || (n_items > 0 && !items_dev)) return fail(F2D_EINVAL, "NULL device table");
-  std::vector<int64_t> prefix(static_cast<size_t>(n_items) + 1);
+  std::vector<int64_t> prefix(static_cast<size_t>(n_items) + 2);
   hipEvent_t e0, e1;
   if (hipEventCreate(&e0) != hipSuccess) return fail(F2D_EHIP, "autotune: hipEventCreate failed");
   if (hipEventCreate(&e1) != hipSuccess) {

@@ -32,6 +32,8 @@ f2d_status fail(f2d_status s, const char* fmt, ...);
 f2d_status ok();
 f2d_status hip_status(hipError_t e, const char* what);
 f2d_status check_tensor(const f2d_tensor* t, const char* name, bool is_output);
+f2d_status check_common(const f2d_tensor* image, const f2d_filter* filter, const f2d_opts* opts,
+                        Problem* pr);
 bool row_aligned(const f2d_tensor& t, size_t bytes);
 int64_t numel(const f2d_tensor& t);
 

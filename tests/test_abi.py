@@ -162,7 +162,7 @@ def test_backward_validation_on_the_host(lib):
 def test_batched_plan_validation_on_the_host(lib):
     item = B.F2dBatchItem(FAKE, FAKE, FAKE, 3, 10, 12, 120, 12, 120, 12)
     items = (B.F2dBatchItem * 2)(item, item)
-    prefix = (ctypes.c_int64 * 3)()
+    prefix = (ctypes.c_int64 * 4)()  # n_items + 1 prefix sums, then the plan's tag
     var = ctypes.c_int32(0)
     assert lib.filter2d_batched_plan(items, 2, B.F32, 4, ctypes.byref(var), prefix) == -B.EINVAL
     assert lib.filter2d_batched_plan(items, 2, B.U8, 3, ctypes.byref(var), prefix) == -B.EUNSUPPORTED
@@ -172,6 +172,46 @@ def test_batched_plan_validation_on_the_host(lib):
     total = lib.filter2d_batched_plan(items, 2, B.F32, 3, ctypes.byref(var), prefix)
     assert total > 0 and var.value >= 1
     assert prefix[0] == 0 and prefix[2] == total and prefix[1] == total // 2
+
+
+def test_batched_plan_tags_the_table(lib):
+    """The plan's last word records the tiling variant and K, so that the
+    kernel can recognise a table planned for another tile shape (whose tile
+    counts would send tiles past an item's planes) and write nothing."""
+    item = B.F2dBatchItem(FAKE, FAKE, FAKE, 3, 100, 300, 30000, 300, 30000, 300)
+    items = (B.F2dBatchItem * 1)(item)
+    tags, totals = {}, {}
+    for v in range(1, lib.filter2d_variant_count(B.PATH_BATCHED) + 1):
+        for k in (3, 7):
+            prefix = (ctypes.c_int64 * 3)()
+            var = ctypes.c_int32(v)
+            totals[v, k] = lib.filter2d_batched_plan(items, 1, B.F32, k, ctypes.byref(var), prefix)
+            assert var.value == v and prefix[1] == totals[v, k]
+            tags[v, k] = prefix[2]
+    assert len(set(tags.values())) == len(tags), "every (variant, K) has its own tag"
+    assert len(set(totals.values())) > 1, "tile counts depend on the variant"
+    assert all(totals[v, 3] == totals[v, 7] for v, _ in totals), "tile counts do not depend on K"
+    # an empty batch still carries the tag after its single prefix word
+    prefix = (ctypes.c_int64 * 2)()
+    var = ctypes.c_int32(1)
+    assert lib.filter2d_batched_plan(items, 0, B.F32, 3, ctypes.byref(var), prefix) == 0
+    assert prefix[0] == 0 and prefix[1] == tags[1, 3]
+
+
+def test_bf16_bank_k_contract(lib):
+    """BF16 banks are built for K in {1, 3, 5}; K = 7 and 9 are rejected on
+    the host with F2D_EUNSUPPORTED (forward, backward and workspace query)."""
+    image = _img(B.BF16, c=16)
+    opts = B.make_opts("bank")
+    for k in (7, 9):
+        filt = _filt(k=k, f_out=64, f_in=16, dtype=B.BF16)
+        assert _fwd(lib, image, filt, opts, [_img(B.F32, c=64)]) == B.EUNSUPPORTED
+        assert "k in {1, 3, 5}" in B.last_error()
+        g = (B.F2dTensor * 1)(_img(B.BF16, c=64))
+        st = lib.filter2d_backward(ctypes.byref(image), ctypes.byref(filt), g, 1, ctypes.byref(opts),
+                                   None, None, None, 0, None)
+        assert st == B.EUNSUPPORTED
+        assert lib.filter2d_backward_workspace(ctypes.byref(image), ctypes.byref(filt), ctypes.byref(opts)) == 0
 
 
 def test_tune_table_roundtrip(lib, tmp_path):
@@ -186,3 +226,4 @@ def test_tune_table_roundtrip(lib, tmp_path):
     assert "[0, 2, 5, 0, 3, 2]" in q.read_text() and "[1, 0, 3, 1, 3, 4]" in q.read_text()
     lib.filter2d_tune_clear()
     assert lib.filter2d_tune_load(b"/nonexistent/tune.json") == B.EINVAL
+
