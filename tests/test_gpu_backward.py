@@ -127,7 +127,7 @@ def test_autograd_wrapper(gpu_lib):
 
 
 def test_finite_differences_on_diff_crops(gpu_lib):
-    """64 x 64 crops of the 16 x 3 x 2048^2 workload, each an independent image
+    """All 8 seeded 64 x 64 crops of the 16 x 3 x 2048^2 workload, each an independent image
     (clamped at the crop's own edges): the FP64 central difference of
     L(x, F) = <filter(x; F), G> (exact for any step since L is linear) along
     random and unit directions against the GPU gradients."""
@@ -135,7 +135,9 @@ def test_finite_differences_on_diff_crops(gpu_lib):
     x0 = wl.diff_image(0)
     g0 = wl.diff_grad(0)
     rng = wl.rng(4, 7)
-    for (oy, ox) in wl.diff_crop_origins()[:4]:
+    origins = wl.diff_crop_origins()
+    assert len(origins) == 8 and (0, 0) in [tuple(o) for o in origins]
+    for (oy, ox) in origins:
         xc = x0[None, :, oy:oy + 64, ox:ox + 64].copy()
         gc = g0[None, :, oy:oy + 64, ox:ox + 64].copy()
         gi, gf = gpu_lib.backward(dev(xc), dev(f), dev(gc))

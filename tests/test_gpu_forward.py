@@ -154,6 +154,37 @@ def test_u8_variants_and_large_taps_wrap(gpu_lib, variant):
         assert torch.equal(outs[2].cpu(), torch.from_numpy(wrap(mm)))
 
 
+@pytest.mark.parametrize("shape", [(1, 1, 1, 1), (1, 2, 9, 13), (2, 3, 70, 517), (1, 2, 131, 260)])
+@pytest.mark.parametrize("k", [9, 11, 31])
+def test_u8_large_k_bit_exact(gpu_lib, shape, k):
+    """K = 9 (templated kernel) and K = 11, 31 (the runtime-K kernel) on the
+    exact integer path: SHARED, and DEPTHWISE with two filters per channel
+    plus the sum-of-squares output, bit-exact against the int64 oracle."""
+    x, f = wl.random_case(30 + k, *shape, k, dtype="u8")
+    y = gpu_lib.forward(dev(x), dev(f[0, 0]))
+    assert torch.equal(y.cpu(), torch.from_numpy(oracle.forward_int(x, f).astype(np.int32)))
+    c = shape[1]
+    fd = wl.rng(40 + k, 1).integers(-8, 9, (2 * c, 1, k, k)).astype(np.int32)
+    gx, gy, m = gpu_lib.forward(dev(x), dev(fd), mode="depthwise", epilogue=gpu_lib.EPI_SUMSQ_PAIRS)
+    ref = oracle.forward_int(x, fd, "depthwise")
+    assert torch.equal(gx.cpu(), torch.from_numpy(ref[:, 0::2].astype(np.int32)))
+    assert torch.equal(gy.cpu(), torch.from_numpy(ref[:, 1::2].astype(np.int32)))
+    mm = oracle.sumsq(ref[:, 0::2], ref[:, 1::2])
+    assert torch.equal(m.cpu(), torch.from_numpy(mm.astype(np.int32)))
+
+
+@pytest.mark.parametrize("k", [9, 13])
+def test_u8_large_k_three_filters_per_channel(gpu_lib, k):
+    """More than two filters per channel (separate launches per filter in the
+    runtime-K kernel)."""
+    x = wl.rng(50 + k, 1).integers(0, 256, (1, 2, 45, 140), dtype=np.uint8)
+    f = wl.rng(50 + k, 2).integers(-100, 101, (6, 1, k, k)).astype(np.int32)
+    outs = gpu_lib.forward(dev(x), dev(f), mode="depthwise")
+    ref = oracle.forward_int(x, f, "depthwise")
+    for j in range(3):
+        assert torch.equal(outs[j].cpu(), torch.from_numpy(ref[:, j::3].astype(np.int32)))
+
+
 def test_u8_unaligned_rows(gpu_lib):
     """Odd row pitch and offset: the word-load and vector-store fast paths
     must switch off; results stay exact."""

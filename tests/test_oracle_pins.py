@@ -440,3 +440,25 @@ def test_golden_constants_match_the_paper_fixtures():
     gray = np.loadtxt(os.path.join(here, "grayscale_weights.txt"))
     assert np.array_equal(lap, wl.LAPLACIAN_8.astype(np.float64))
     assert np.array_equal(gray, wl.GRAY_RGB)
+
+
+def test_rel_l2_acceptance_metric_hand_values():
+    """The acceptance metric ||a - ref|| / ||ref|| against values worked by
+    hand: a swapped numerator and denominator, a missing square root or a
+    normalisation by ||a|| instead of ||ref|| all fail one of these."""
+    ref = np.array([3.0, 4.0])                          # ||ref|| = 5
+    assert oracle.rel_l2(np.array([3.0, 4.5]), ref) == pytest.approx(0.1, rel=1e-15)
+    assert oracle.rel_l2(np.array([3.0, 14.0]), ref) == pytest.approx(2.0, rel=1e-15)
+    ref3 = np.array([[1.0, 2.0, 2.0]])                  # ||ref|| = 3
+    assert oracle.rel_l2(np.array([[1.0, 2.0, 2.3]]), ref3) == pytest.approx(0.1, rel=1e-13)
+    # normalised by the reference: (3, 4) against (6, 8) is 5 / 10, not 5 / 5
+    assert oracle.rel_l2(np.array([3.0, 4.0]), np.array([6.0, 8.0])) == pytest.approx(0.5, rel=1e-15)
+    assert oracle.rel_l2(np.array([6.0, 8.0]), np.array([3.0, 4.0])) == pytest.approx(1.0, rel=1e-15)
+    # squares, not absolute values: (0, 3) vs (4, 0) differ by (-4, 3), norm 5, over ||(4, 0)|| = 4
+    assert oracle.rel_l2(np.array([0.0, 3.0]), np.array([4.0, 0.0])) == pytest.approx(1.25, rel=1e-15)
+    assert oracle.rel_l2(ref, ref) == 0.0
+    # an all-zero reference falls back to the absolute norm of the difference
+    assert oracle.rel_l2(np.array([0.0, 0.3, 0.4]), np.zeros(3)) == pytest.approx(0.5, rel=1e-15)
+    # float32 inputs are promoted before squaring (no overflow at 1e30)
+    big = np.array([1e30, 1e30], dtype=np.float32)
+    assert oracle.rel_l2(big * np.float32(1.5), big) == pytest.approx(0.5, rel=1e-6)
