@@ -551,6 +551,68 @@ def profile_sobel(torch, B, wl, steps):
     print(json.dumps({"profile": "sobel-8k", "variant": variant, "steps": steps}), flush=True)
 
 
+TRAFFIC_KERNELS = {
+    # key in profiles/traffic.json -> (kernel-name test, algorithmic bytes, sources)
+    "bank_bf16_k5_fwd_f32out": (lambda n: "k_bank_conv" in n and "ring" not in n and "_ws" not in n,
+                                lambda: bank_bytes(5)["fwd_f32out"], BANK_SRC),
+    "bank_bf16_k5_dgrad": (lambda n: "k_bank_conv_ring" in n, lambda: bank_bytes(5)["dgrad"], BANK_SRC),
+    "bank_bf16_k5_wgrad": (lambda n: "k_bank_wgrad" in n, lambda: bank_bytes(5)["wgrad"], BANK_SRC),
+}
+
+
+def traffic_from(fetch_dir, write_dir):
+    """HBM bytes per launch of the headline kernels from two rocprofv3 counter
+    runs of `bench.py --profile` (FETCH_SIZE, then WRITE_SIZE, in KiB per
+    dispatch), each scaled by what the same counter reads for the run's final
+    1 GiB device copy (whose bytes are known); written to profiles/traffic.json
+    with the kernel sources' hash."""
+    import csv
+    import glob
+    import re
+
+    def rows(d):
+        out = []
+        for path in glob.glob(os.path.join(d, "**", "*counter_collection.csv"), recursive=True):
+            with open(path) as f:
+                out.extend(csv.DictReader(f))
+        if not out:
+            raise SystemExit(f"no counter_collection.csv under {d}")
+        return out
+
+    def per_kernel(d, counter):
+        vals = {}
+        for r in rows(d):
+            if r.get("Counter_Name") != counter:
+                continue
+            vals.setdefault(r["Kernel_Name"], []).append(float(r["Counter_Value"]))
+        return vals
+
+    fetch, write = per_kernel(fetch_dir, "FETCH_SIZE"), per_kernel(write_dir, "WRITE_SIZE")
+    copy = [n for n in fetch if re.search(r"copy|Copy", n) and "bank" not in n]
+    if not copy:
+        raise SystemExit("no device copy kernel in the counter runs")
+    gib_kib = float(1 << 20)
+    ffac = gib_kib / float(np.median(fetch[copy[-1]]))
+    wfac = gib_kib / float(np.median(write[copy[-1]]))
+    path = os.path.join(ROOT, "profiles", "traffic.json")
+    table = json.load(open(path)) if os.path.exists(path) else {}
+    for key, (match, alg, srcs) in TRAFFIC_KERNELS.items():
+        names = [n for n in fetch if match(n)]
+        if not names:
+            continue
+        fk = float(np.median(fetch[names[0]]))
+        wk = float(np.median(write[names[0]]))
+        fb, wb = fk * 1024 * ffac, wk * 1024 * wfac
+        table[key] = {"src_sha": sha_of(*srcs), "source": ", ".join(srcs), "kernel": names[0][:160],
+                      "bytes_per_launch": int(fb + wb), "fetch_bytes": int(fb), "write_bytes": int(wb),
+                      "fetch_kib_raw_median": fk, "write_kib_raw_median": wk,
+                      "fetch_factor": round(ffac, 4), "write_factor": round(wfac, 4),
+                      "algorithmic_bytes": alg(), "traffic_over_algorithmic": round((fb + wb) / alg(), 4)}
+    with open(path, "w") as f:
+        json.dump(table, f, indent=1)
+    print(json.dumps({k: table[k].get("traffic_over_algorithmic") for k in table}), flush=True)
+
+
 def write_ceiling(torch, reps):
     """What the device's memory system sustains for plain writes and copies:
     torch's fill kernel over 1.19 GB (the size of the Sobel outputs) and 4.3 GB
@@ -586,10 +648,15 @@ def main():
                     help="rocprofv3 run: the 8K Sobel kernel --steps times + a 1 GiB copy")
     ap.add_argument("--write-ceiling", action="store_true",
                     help="measure the device's plain-write and copy rates")
+    ap.add_argument("--traffic-from", nargs=2, metavar=("FETCH_DIR", "WRITE_DIR"),
+                    help="write profiles/traffic.json from two rocprofv3 --pmc runs of --profile")
     ap.add_argument("--oracle-one-core", type=int, default=0, help=argparse.SUPPRESS)
     args = ap.parse_args()
     if args.oracle_one_core:
         oracle_one_core(args.oracle_one_core, args.k)
+        return
+    if args.traffic_from:
+        traffic_from(*args.traffic_from)
         return
     if args.gpus != 1:
         print(f"bench.py measures one GPU only (got --gpus {args.gpus}): the filter runs on one GPU's "

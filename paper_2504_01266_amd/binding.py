@@ -181,7 +181,7 @@ def forward(image, filt, mode="shared", epilogue=EPI_NONE, rows=None, outs=None,
         co = filt.size(0) if m == BANK else c
         outs = [torch.empty((n, co, r1 - r0, w), dtype=odt, device=image.device)
                 for _ in range(nout)]
-    descs = (F2dTensor * len(outs))(*[tensor_desc(o) for o in outs])
+    descs = (F2dTensor * len(outs))(*[tensor_desc(_as4(o)) for o in outs])
     opts = make_opts(m, epilogue, (r0, r1), variant, border)
     _check(lib.filter2d_forward(ctypes.byref(tensor_desc(image)), ctypes.byref(fd),
                                 ctypes.byref(opts), descs, len(outs), _stream()))
@@ -204,7 +204,7 @@ def forward_separable(image, a, b, rows=None, out=None):
     opts = make_opts("shared", EPI_NONE, (r0, r1))
     _check(lib.filter2d_forward_separable(ctypes.byref(tensor_desc(image)), ctypes.c_void_p(a.data_ptr()),
                                           ctypes.c_void_p(b.data_ptr()), a.numel(), ctypes.byref(opts),
-                                          ctypes.byref(tensor_desc(out)), _stream()))
+                                          ctypes.byref(tensor_desc(_as4(out))), _stream()))
     return out
 
 
@@ -265,7 +265,7 @@ def autotune_forward(image, filt, mode="shared", epilogue=EPI_NONE, rows=None, r
     co = filt.size(0) if m == BANK else c
     outs = [torch.empty((n, co, r1 - r0, w), dtype=odt, device=image.device)
             for _ in range(out_count(m, filt.shape, c, epilogue))]
-    descs = (F2dTensor * len(outs))(*[tensor_desc(o) for o in outs])
+    descs = (F2dTensor * len(outs))(*[tensor_desc(_as4(o)) for o in outs])
     best = ctypes.c_int32(0)
     _check(lib.filter2d_autotune_forward(ctypes.byref(tensor_desc(image)), ctypes.byref(fd),
                                          ctypes.byref(make_opts(m, epilogue, (r0, r1))), descs,
