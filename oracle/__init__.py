@@ -11,6 +11,9 @@ Section 4.2.5):
 
 * forward:      Y[n][o][y][x] = sum_{i in inputs(o)} sum_{u,v} F[o|i][u][v] *
                                 X[n][i][cl_H(y+u-r)][cl_W(x+v-r)]
+                (binary64, int64, or binary32 in a stated order; clamp-to-edge
+                or zero borders; 8-bit outputs by clamping and rounding)
+* upsample:     nearest-neighbour, integer factor (Section 4.2.3)
 * grad_input:   the adjoint of the forward map in X, in scatter form
 * grad_filter:  the adjoint in F, with Neumaier compensated summation
 
@@ -34,6 +37,8 @@ _i64 = ctypes.c_int64
 _i32 = ctypes.c_int32
 _dp = ctypes.POINTER(ctypes.c_double)
 _lp = ctypes.POINTER(ctypes.c_int64)
+_fp = ctypes.POINTER(ctypes.c_float)
+_bp = ctypes.POINTER(ctypes.c_uint8)
 
 
 def _load():
@@ -51,12 +56,19 @@ def _load():
                                             _i32, _i64, _i64, _dp]
     lib.oracle_forward_i64.argtypes = [_lp, _i64, _i64, _i64, _i64, _lp, _i64, _i64, _i64, _i32,
                                        _i64, _i64, _lp]
+    lib.oracle_forward_zero_i64.argtypes = [_lp, _i64, _i64, _i64, _i64, _lp, _i64, _i64, _i64, _i32,
+                                            _i64, _i64, _lp]
+    lib.oracle_forward_f32fma.argtypes = [_fp, _i64, _i64, _i64, _i64, _fp, _i64, _i64, _i64, _i32,
+                                          _i32, _fp]
+    lib.oracle_u8_from_f32.argtypes = [_fp, _i64, _bp]
+    lib.oracle_u8_from_i64.argtypes = [_lp, _i64, _bp]
     lib.oracle_sumsq_i64.argtypes = [_lp, _lp, _i64, _lp]
     lib.oracle_grad_input_f64.argtypes = [_dp, _i64, _i64, _i64, _i64, _dp, _i64, _i64, _i64,
                                           _i32, _dp]
     lib.oracle_grad_filter_f64.argtypes = [_dp, _dp, _i64, _i64, _i64, _i64, _i64, _i64, _i64,
                                            _i32, _dp]
     for name in ("oracle_forward_f64", "oracle_forward_zero_f64", "oracle_forward_i64", "oracle_sumsq_i64",
+                 "oracle_forward_zero_i64", "oracle_forward_f32fma", "oracle_u8_from_f32", "oracle_u8_from_i64",
                  "oracle_grad_input_f64", "oracle_grad_filter_f64", "oracle_num_threads"):
         getattr(lib, name).restype = ctypes.c_int
     _lib = lib
@@ -119,8 +131,10 @@ def forward(x, f, mode="shared", rows=None, border="clamp"):
     return out
 
 
-def forward_int(x, f, mode="shared", rows=None):
-    """Exact int64 forward filter (the integer path)."""
+def forward_int(x, f, mode="shared", rows=None, border="clamp"):
+    """Exact int64 forward filter (the integer path); border "clamp" or "zero"."""
+    if border not in ("clamp", "zero"):
+        raise ValueError("border must be 'clamp' or 'zero'")
     m = _mode(mode)
     x = np.ascontiguousarray(_as4(x), dtype=np.int64)
     f = np.ascontiguousarray(_filt4(f), dtype=np.int64)
@@ -128,11 +142,61 @@ def forward_int(x, f, mode="shared", rows=None):
     FO, FI, K, _ = f.shape
     y0, y1 = (0, H) if rows is None else rows
     out = np.empty((N, _out_channels(C, FO, m), y1 - y0, W), np.int64)
-    rc = _load().oracle_forward_i64(x.ctypes.data_as(_lp), N, C, H, W, f.ctypes.data_as(_lp),
-                                    FO, FI, K, m, y0, y1, out.ctypes.data_as(_lp))
+    fn = _load().oracle_forward_i64 if border == "clamp" else _load().oracle_forward_zero_i64
+    rc = fn(x.ctypes.data_as(_lp), N, C, H, W, f.ctypes.data_as(_lp), FO, FI, K, m, y0, y1,
+            out.ctypes.data_as(_lp))
     if rc != 0:
-        raise ValueError("oracle_forward_i64: invalid arguments")
+        raise ValueError("oracle integer forward: invalid arguments")
     return out
+
+
+def forward_f32(x, f, mode="shared", border="clamp"):
+    """The forward sum in binary32 in a fixed order (accumulator +0, one fused
+    multiply-add per term: input channel, tap row, tap column), the precision
+    of the paper's float filter taps (Section 4.2.4).  x is converted to
+    float32 (exact for 8-bit values).  Returns float32 [N][C_out][H][W]."""
+    if border not in ("clamp", "zero"):
+        raise ValueError("border must be 'clamp' or 'zero'")
+    m = _mode(mode)
+    x = np.ascontiguousarray(_as4(x), dtype=np.float32)
+    f = np.ascontiguousarray(_filt4(f), dtype=np.float32)
+    N, C, H, W = x.shape
+    FO, FI, K, _ = f.shape
+    out = np.empty((N, _out_channels(C, FO, m), H, W), np.float32)
+    rc = _load().oracle_forward_f32fma(x.ctypes.data_as(_fp), N, C, H, W, f.ctypes.data_as(_fp), FO, FI,
+                                       K, m, 1 if border == "zero" else 0, out.ctypes.data_as(_fp))
+    if rc != 0:
+        raise ValueError("oracle_forward_f32fma: invalid arguments")
+    return out
+
+
+def to_u8(a):
+    """8-bit image from sums: float32 sums are clamped to [0, 255] and rounded
+    to nearest, ties to even; integer sums are clamped."""
+    a = np.asarray(a)
+    if a.dtype.kind == "f":
+        src = np.ascontiguousarray(a, dtype=np.float32)
+        out = np.empty(src.shape, np.uint8)
+        _load().oracle_u8_from_f32(src.ctypes.data_as(_fp), src.size, out.ctypes.data_as(_bp))
+    else:
+        src = np.ascontiguousarray(a, dtype=np.int64)
+        out = np.empty(src.shape, np.uint8)
+        _load().oracle_u8_from_i64(src.ctypes.data_as(_lp), src.size, out.ctypes.data_as(_bp))
+    return out
+
+
+def upsample_nearest(x, s):
+    """Nearest-neighbour upsampling by an integer factor s >= 1 (the paper's
+    upsampling, Section 4.2.3): output pixel (Y, X) copies input pixel
+    (Y // s, X // s); the output is s times taller and wider."""
+    s = int(s)
+    if s < 1:
+        raise ValueError("scale must be >= 1")
+    x = np.asarray(x)
+    H, W = x.shape[-2], x.shape[-1]
+    ys = np.arange(H * s) // s
+    xs = np.arange(W * s) // s
+    return x[..., ys[:, None], xs[None, :]]
 
 
 def sumsq(a, b):

@@ -166,6 +166,107 @@ int oracle_forward_i64(const int64_t* x, int64_t N, int64_t C, int64_t H, int64_
   return 0;
 }
 
+/* Zero-border int64 forward (out-of-image neighbours add nothing). */
+int oracle_forward_zero_i64(const int64_t* x, int64_t N, int64_t C, int64_t H, int64_t W,
+                       const int64_t* f, int64_t FO, int64_t FI, int64_t K, int32_t mode,
+                       int64_t y0, int64_t y1, int64_t* out) {
+  int64_t CO = out_channels(C, FO, FI, K, mode);
+  if (CO < 0 || N < 0 || H < 0 || W < 0 || y0 < 0 || y1 < y0 || y1 > H) return -1;
+  if (N == 0 || H == 0 || W == 0 || y1 == y0) return 0;
+  int64_t r = (K - 1) / 2, rows = y1 - y0;
+  int64_t planes = N * CO;
+#pragma omp parallel for schedule(dynamic, 1)
+  for (int64_t p = 0; p < planes * rows; ++p) {
+    int64_t n = (p / rows) / CO, o = (p / rows) % CO, y = y0 + p % rows;
+    for (int64_t xx = 0; xx < W; ++xx) {
+      int64_t acc = 0;
+      for (int64_t t = 0; t < n_inputs(C, mode); ++t) {
+        int64_t i, fo, fi;
+        input_of(o, t, C, FO, mode, &i, &fo, &fi);
+        const int64_t* xi = x + (n * C + i) * H * W;
+        const int64_t* ff = f + (fo * FI + fi) * K * K;
+        for (int64_t u = 0; u < K; ++u) {
+          int64_t sy = y + u - r;
+          if (sy < 0 || sy >= H) continue;
+          for (int64_t v = 0; v < K; ++v) {
+            int64_t sx = xx + v - r;
+            if (sx < 0 || sx >= W) continue;
+            acc += ff[u * K + v] * xi[sy * W + sx];
+          }
+        }
+      }
+      out[((n * CO + o) * rows + (y - y0)) * W + xx] = acc;
+    }
+  }
+  return 0;
+}
+
+/*
+ * The forward sum in binary32, as the paper's sharpen computes it (float
+ * filter taps times 8-bit pixel values, Section 4.2.4).  Here the order of the
+ * sum is fixed, because with u8 outputs the rounding decides an integer: the
+ * accumulator starts at +0 and takes one fused multiply-add (a single rounding,
+ * C's fmaf) per term, input channels outermost, then tap rows u, then tap
+ * columns v.  With zero borders an out-of-image neighbour is skipped (adding
+ * F * 0 with a fused multiply-add leaves the accumulator unchanged, so either
+ * form gives the same value).  Whole images: out is [N][C_out][H][W].
+ */
+int oracle_forward_f32fma(const float* x, int64_t N, int64_t C, int64_t H, int64_t W, const float* f,
+                          int64_t FO, int64_t FI, int64_t K, int32_t mode, int32_t zero_border,
+                          float* out) {
+  int64_t CO = out_channels(C, FO, FI, K, mode);
+  if (CO < 0 || N < 0 || H < 0 || W < 0) return -1;
+  if (N == 0 || H == 0 || W == 0) return 0;
+  int64_t r = (K - 1) / 2;
+#pragma omp parallel for schedule(dynamic, 1)
+  for (int64_t p = 0; p < N * CO * H; ++p) {
+    int64_t n = (p / H) / CO, o = (p / H) % CO, y = p % H;
+    for (int64_t xx = 0; xx < W; ++xx) {
+      float acc = 0.0f;
+      for (int64_t t = 0; t < n_inputs(C, mode); ++t) {
+        int64_t i, fo, fi;
+        input_of(o, t, C, FO, mode, &i, &fo, &fi);
+        const float* xi = x + (n * C + i) * H * W;
+        const float* ff = f + (fo * FI + fi) * K * K;
+        for (int64_t u = 0; u < K; ++u) {
+          int64_t sy = y + u - r;
+          if (zero_border && (sy < 0 || sy >= H)) continue;
+          for (int64_t v = 0; v < K; ++v) {
+            int64_t sx = xx + v - r;
+            if (zero_border && (sx < 0 || sx >= W)) continue;
+            acc = fmaf(ff[u * K + v], xi[cl(sy, H) * W + cl(sx, W)], acc);
+          }
+        }
+      }
+      out[((n * CO + o) * H + y) * W + xx] = acc;
+    }
+  }
+  return 0;
+}
+
+/*
+ * 8-bit outputs.  The paper stores its float sums in 8-bit images without
+ * saying how; the reading here is OpenCV's conversion: clamp to [0, 255] and
+ * round to the nearest integer, ties to even (rintf in the default rounding
+ * mode).  Integer sums are clamped.
+ */
+int oracle_u8_from_f32(const float* a, int64_t count, uint8_t* out) {
+  if (count < 0) return -1;
+  for (int64_t k = 0; k < count; ++k) {
+    float v = a[k];
+    if (!(v > 0.0f)) v = 0.0f;
+    if (v > 255.0f) v = 255.0f;
+    out[k] = (uint8_t)rintf(v);
+  }
+  return 0;
+}
+
+int oracle_u8_from_i64(const int64_t* a, int64_t count, uint8_t* out) {
+  if (count < 0) return -1;
+  for (int64_t k = 0; k < count; ++k) out[k] = (uint8_t)(a[k] < 0 ? 0 : (a[k] > 255 ? 255 : a[k]));
+  return 0;
+}
+
 int oracle_sumsq_i64(const int64_t* a, const int64_t* b, int64_t count, int64_t* out) {
   if (count < 0) return -1;
 #pragma omp parallel for schedule(static)

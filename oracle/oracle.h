@@ -22,7 +22,8 @@
  *                   grayscale weighting of Section 4.2.5).
  *
  * Arrays are dense, row-major: images [N][C][H][W], filters [FO][FI][K][K].
- * Floating-point arithmetic is IEEE binary64; the integer path is int64.
+ * Floating-point arithmetic is IEEE binary64, except oracle_forward_f32fma
+ * (binary32 in a stated order, for 8-bit outputs); the integer path is int64.
  * Every function returns 0 on success and a negative value on bad arguments.
  */
 #ifndef FILTER2D_ORACLE_H
@@ -55,6 +56,24 @@ int oracle_forward_zero_f64(const double* x, int64_t N, int64_t C, int64_t H, in
 int oracle_forward_i64(const int64_t* x, int64_t N, int64_t C, int64_t H, int64_t W,
                        const int64_t* f, int64_t FO, int64_t FI, int64_t K, int32_t mode,
                        int64_t y0, int64_t y1, int64_t* out);
+
+/* As oracle_forward_i64 with zero borders. */
+int oracle_forward_zero_i64(const int64_t* x, int64_t N, int64_t C, int64_t H, int64_t W,
+                            const int64_t* f, int64_t FO, int64_t FI, int64_t K, int32_t mode,
+                            int64_t y0, int64_t y1, int64_t* out);
+
+/* The forward sum in binary32 with a fixed order: acc = +0, then one fused
+ * multiply-add per term (input channel, then tap row u, then tap column v).
+ * zero_border != 0: out-of-image neighbours are skipped; else clamp-to-edge.
+ * Whole images; out: [N][C_out][H][W]. */
+int oracle_forward_f32fma(const float* x, int64_t N, int64_t C, int64_t H, int64_t W, const float* f,
+                          int64_t FO, int64_t FI, int64_t K, int32_t mode, int32_t zero_border,
+                          float* out);
+
+/* 8-bit conversion: clamp to [0, 255], then round to nearest, ties to even
+ * (floats) or keep (integers). */
+int oracle_u8_from_f32(const float* a, int64_t count, uint8_t* out);
+int oracle_u8_from_i64(const int64_t* a, int64_t count, uint8_t* out);
 
 /* out[k] = a[k]^2 + b[k]^2 (the gradient-magnitude epilogue, no square root). */
 int oracle_sumsq_i64(const int64_t* a, const int64_t* b, int64_t count, int64_t* out);
