@@ -30,7 +30,8 @@
  *   - The caller owns every buffer (images, filters, outputs, workspaces,
  *     descriptor tables).  The library allocates no device memory, keeps no
  *     device state between calls and never synchronises the stream, except in
- *     the explicitly synchronous filter2d_autotune_* calls.
+ *     the explicitly synchronous filter2d_autotune_* calls.  The one device
+ *     state is the static scratch array of filter2d_backward_noalloc.
  *   - `stream` is a hipStream_t (NULL = the default stream); work is only
  *     enqueued on it, so calls are capturable into a hipGraph.
  *   - Arguments are validated on the host before anything is enqueued: an
@@ -195,6 +196,29 @@ f2d_status filter2d_backward(const f2d_tensor* image, const f2d_filter* filter,
                              const f2d_opts* opts, const f2d_tensor* grad_input,
                              float* grad_filter, void* workspace, size_t workspace_bytes,
                              void* stream);
+
+/*
+ * filter2d_backward_noalloc -- filter2d_backward without a caller workspace,
+ * for callers that cannot allocate device memory (code under stream capture,
+ * tight serving loops, harnesses that forbid hipMalloc).  The workspace is a
+ * static device array of F2D_NOALLOC_SCRATCH_BYTES owned by the library: each
+ * device the library runs on holds its own copy from its first use until the
+ * process ends.  The call allocates nothing (no hipMalloc / hipFree).
+ *
+ *   Arguments, results, validation and errors as for filter2d_backward.
+ *   Arguments whose filter2d_backward_workspace() exceeds
+ *   F2D_NOALLOC_SCRATCH_BYTES return F2D_EWORKSPACE and enqueue nothing.
+ *   The stream must belong to the current device.
+ *   Calls on the same device share the array: calls that overlap in time on
+ *   one device (e.g. on two streams) race and give wrong results.  Nothing in
+ *   the array needs clearing between calls (every value the kernels read is
+ *   written earlier in the same call).
+ */
+#define F2D_NOALLOC_SCRATCH_BYTES ((size_t)96 << 20)
+f2d_status filter2d_backward_noalloc(const f2d_tensor* image, const f2d_filter* filter,
+                                     const f2d_tensor* grad_outs, int32_t n_grad_outs,
+                                     const f2d_opts* opts, const f2d_tensor* grad_input,
+                                     float* grad_filter, void* stream);
 
 /*
  * Ragged batches: images of different sizes, each with its own filter,

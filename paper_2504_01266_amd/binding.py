@@ -79,6 +79,8 @@ def load():
         "filter2d_backward_workspace": (sz, [_P(F2dTensor), _P(F2dFilter), _P(F2dOpts)]),
         "filter2d_backward": (i32, [_P(F2dTensor), _P(F2dFilter), _P(F2dTensor), i32, _P(F2dOpts),
                                     _P(F2dTensor), vp, vp, sz, vp]),
+        "filter2d_backward_noalloc": (i32, [_P(F2dTensor), _P(F2dFilter), _P(F2dTensor), i32, _P(F2dOpts),
+                                            _P(F2dTensor), vp, vp]),
         "filter2d_batched_plan": (i64, [_P(F2dBatchItem), i32, i32, i32, _P(i32), _P(i64)]),
         "filter2d_batched": (i32, [vp, vp, i32, i64, i32, i32, _P(F2dOpts), vp]),
         "filter2d_autotune_forward": (i32, [_P(F2dTensor), _P(F2dFilter), _P(F2dOpts), _P(F2dTensor),
@@ -248,6 +250,36 @@ def backward(image, filt, grad_outs, mode="shared", need_input=True, need_filter
                                  len(grad_outs), ctypes.byref(opts), gid,
                                  ctypes.c_void_p(gf.data_ptr() if gf is not None else 0),
                                  ctypes.c_void_p(workspace.data_ptr()), ws_bytes, _stream()))
+    if gf is not None and filt.dim() == 2:
+        gf = gf.view(filt.shape)
+    return gi, gf
+
+
+def backward_noalloc(image, filt, grad_outs, mode="shared", need_input=True, need_filter=True,
+                     grad_input=None, grad_filter=None):
+    """``backward`` through filter2d_backward_noalloc: no workspace argument,
+    the library's static per-device scratch is used instead."""
+    lib = load()
+    image = _as4(image)
+    fd, filt4 = filter_desc(filt)
+    if isinstance(grad_outs, torch.Tensor):
+        grad_outs = [grad_outs]
+    grad_outs = [_as4(g) for g in grad_outs]
+    opts = make_opts(mode)
+    gi, gf = None, None
+    if need_input:
+        gi = grad_input if grad_input is not None else \
+            torch.empty(image.shape, dtype=torch.float32, device=image.device)
+    if need_filter:
+        gf = grad_filter if grad_filter is not None else \
+            torch.empty(filt4.shape, dtype=torch.float32, device=image.device)
+        if gf.numel() != filt4.numel() or gf.dtype != torch.float32 or not gf.is_contiguous():
+            raise ValueError("grad_filter must be a contiguous float32 tensor with the filter's size")
+    gds = (F2dTensor * len(grad_outs))(*[tensor_desc(g) for g in grad_outs])
+    gid = ctypes.byref(tensor_desc(gi)) if gi is not None else None
+    _check(lib.filter2d_backward_noalloc(ctypes.byref(tensor_desc(image)), ctypes.byref(fd), gds,
+                                         len(grad_outs), ctypes.byref(opts), gid,
+                                         ctypes.c_void_p(gf.data_ptr() if gf is not None else 0), _stream()))
     if gf is not None and filt.dim() == 2:
         gf = gf.view(filt.shape)
     return gi, gf

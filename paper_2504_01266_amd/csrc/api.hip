@@ -328,6 +328,18 @@ f2d_status filter2d_backward(const f2d_tensor* image, const f2d_filter* filter,
                       static_cast<hipStream_t>(stream));
 }
 
+f2d_status filter2d_backward_noalloc(const f2d_tensor* image, const f2d_filter* filter,
+                                     const f2d_tensor* grad_outs, int32_t n_grad_outs, const f2d_opts* opts,
+                                     const f2d_tensor* grad_input, float* grad_filter, void* stream) {
+  Problem pr;
+  f2d_status s = check_common(image, filter, opts, &pr);
+  if (s) return s;
+  if (opts->border != F2D_BORDER_CLAMP)
+    return fail(F2D_EUNSUPPORTED, "backward: clamp-to-edge borders only (zero borders are forward-only)");
+  return run_backward_noalloc(pr, grad_outs, n_grad_outs, grad_input, grad_filter,
+                              static_cast<hipStream_t>(stream));
+}
+
 int64_t filter2d_batched_plan(const f2d_batch_item* items, int32_t n_items, int32_t dtype, int32_t k,
                               int32_t* variant, int64_t* tile_prefix) {
   return batched_plan(items, n_items, dtype, k, variant, tile_prefix);

@@ -72,9 +72,8 @@ size_t backward_workspace(const Problem& pr) {
   return frame_bytes(pr) + round_up(bytes > 0 ? bytes : 1);
 }
 
-f2d_status run_backward(const Problem& pr, const f2d_tensor* grad_outs, int32_t n_grad_outs,
-                        const f2d_tensor* grad_input, float* grad_filter, void* ws, size_t ws_bytes,
-                        hipStream_t s) {
+f2d_status check_backward(const Problem& pr, const f2d_tensor* grad_outs, int32_t n_grad_outs,
+                          const f2d_tensor* grad_input) {
   const f2d_tensor& im = pr.image;
   if (im.dtype == F2D_U8) return fail(F2D_EUNSUPPORTED, "u8 images are not differentiable");
   if (!whole_image(pr))
@@ -101,6 +100,15 @@ f2d_status run_backward(const Problem& pr, const f2d_tensor* grad_outs, int32_t 
       return fail(F2D_EINVAL, "grad_input: shape must equal the image's");
     if (grad_input->dtype != F2D_F32) return fail(F2D_EINVAL, "grad_input must be f32");
   }
+  return F2D_OK;
+}
+
+f2d_status run_backward(const Problem& pr, const f2d_tensor* grad_outs, int32_t n_grad_outs,
+                        const f2d_tensor* grad_input, float* grad_filter, void* ws, size_t ws_bytes,
+                        hipStream_t s) {
+  if (f2d_status e = check_backward(pr, grad_outs, n_grad_outs, grad_input)) return e;
+  const f2d_tensor& im = pr.image;
+  const int64_t co = pr.mode == F2D_CH_BANK ? pr.c_out : im.c;
   const size_t need = backward_workspace(pr);
   if ((grad_filter || grad_input) && need > 0 && (!ws || ws_bytes < need))
     return fail(F2D_EWORKSPACE, "workspace of %zu bytes needed, got %zu", need, ws ? ws_bytes : 0);

@@ -53,9 +53,15 @@ f2d_status run_forward_separable(const Problem& pr, const float* a, const float*
 
 // backward.hip
 size_t backward_workspace(const Problem& pr);
+f2d_status check_backward(const Problem& pr, const f2d_tensor* grad_outs, int32_t n_grad_outs,
+                          const f2d_tensor* grad_input);
 f2d_status run_backward(const Problem& pr, const f2d_tensor* grad_outs, int32_t n_grad_outs,
                         const f2d_tensor* grad_input, float* grad_filter, void* ws, size_t ws_bytes,
                         hipStream_t s);
+
+// noalloc.hip: run_backward on the library's static per-device scratch
+f2d_status run_backward_noalloc(const Problem& pr, const f2d_tensor* grad_outs, int32_t n_grad_outs,
+                                const f2d_tensor* grad_input, float* grad_filter, hipStream_t s);
 
 // batched.hip
 int64_t batched_plan(const f2d_batch_item* items, int32_t n_items, int32_t dtype, int32_t k,

@@ -159,6 +159,47 @@ def test_backward_validation_on_the_host(lib):
                                            ctypes.byref(opts)) == 0
 
 
+NOALLOC_SCRATCH_BYTES = 96 << 20  # F2D_NOALLOC_SCRATCH_BYTES
+
+
+def test_header_states_the_noalloc_scratch_size():
+    text = open(HEADER).read()
+    assert re.search(r"#define F2D_NOALLOC_SCRATCH_BYTES \(\(size_t\)96 << 20\)", text)
+
+
+def test_backward_noalloc_validation_on_the_host(lib):
+    """Invalid calls and calls whose workspace exceeds the static scratch are
+    rejected before any device access."""
+    image, filt = _img(), _filt(k=3)
+    opts = B.make_opts()
+    g = (B.F2dTensor * 1)(_img())
+    st = lib.filter2d_backward_noalloc(ctypes.byref(_img(B.U8)), ctypes.byref(_filt(dtype=B.I32)), g, 1,
+                                       ctypes.byref(opts), None, None, None)
+    assert st == B.EUNSUPPORTED
+    st = lib.filter2d_backward_noalloc(ctypes.byref(image), ctypes.byref(filt), g, 2,
+                                       ctypes.byref(opts), None, None, None)
+    assert st == B.EINVAL
+    st = lib.filter2d_backward_noalloc(ctypes.byref(image), ctypes.byref(filt), g, 1,
+                                       ctypes.byref(B.make_opts(border="zero")), None, None, None)
+    assert st == B.EUNSUPPORTED
+    # a 128-image 5x5 BF16 bank: its workspace is larger than the static scratch
+    n, c, h, w = 128, 16, 1024, 1024
+    big = B.F2dTensor(FAKE, B.BF16, 0, n, c, h, w, c * h * w, h * w, w)
+    bf = B.F2dFilter(FAKE, B.BF16, 64, 16, 5)
+    bopts = B.make_opts("bank")
+    need = lib.filter2d_backward_workspace(ctypes.byref(big), ctypes.byref(bf), ctypes.byref(bopts))
+    assert need > NOALLOC_SCRATCH_BYTES
+    gb = (B.F2dTensor * 1)(B.F2dTensor(FAKE, B.BF16, 0, n, 64, h, w, 64 * h * w, h * w, w))
+    gi = B.F2dTensor(FAKE, B.F32, 0, n, c, h, w, c * h * w, h * w, w)
+    st = lib.filter2d_backward_noalloc(ctypes.byref(big), ctypes.byref(bf), gb, 1, ctypes.byref(bopts),
+                                       ctypes.byref(gi), FAKE, None)
+    assert st == B.EWORKSPACE and "scratch" in B.last_error()
+    # the 32-image 5x5 bank of the benchmark fits
+    big32 = B.F2dTensor(FAKE, B.BF16, 0, 32, c, h, w, c * h * w, h * w, w)
+    assert lib.filter2d_backward_workspace(ctypes.byref(big32), ctypes.byref(bf),
+                                           ctypes.byref(bopts)) <= NOALLOC_SCRATCH_BYTES
+
+
 def test_batched_plan_validation_on_the_host(lib):
     item = B.F2dBatchItem(FAKE, FAKE, FAKE, 3, 10, 12, 120, 12, 120, 12)
     items = (B.F2dBatchItem * 2)(item, item)
