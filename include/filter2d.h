@@ -12,7 +12,7 @@
  * offset (u-r, v-r)) and clamp-to-edge borders cl_n(t) = min(max(t,0), n-1)
  * applied to each axis.  The paper's sharpen skips out-of-image neighbours
  * (Section 4.2.4); that rule is F2D_BORDER_ZERO (X reads as 0 outside the
- * image), implemented for the FP32 forward.
+ * image), implemented for the FP32 forward and the 8-bit SHARED forward.
  *
  * Channel modes (F is always a contiguous [f_out][f_in][k][k] array):
  *   F2D_CH_SHARED     f_out = f_in = 1: the same filter on every channel
@@ -40,7 +40,8 @@
  *   - A launch failure returns F2D_EHIP with the HIP error text.  Faults that
  *     happen while the kernels run are reported by the next synchronising
  *     HIP call, as for any asynchronous launch.
- *   - Strides are in ELEMENTS; the x (column) stride is always 1.
+ *   - Strides are in ELEMENTS; the x (column) stride is 1 except for the
+ *     interleaved 8-bit layouts (f2d_tensor.stride_w).
  *   - Outputs must not overlap inputs.
  */
 #ifndef FILTER2D_H
@@ -69,8 +70,10 @@ typedef int32_t f2d_status;
 /* border rules */
 #define F2D_BORDER_CLAMP 0 /* replicate the edge pixel: cl_n(t) = min(max(t,0), n-1) */
 #define F2D_BORDER_ZERO 1  /* out-of-image neighbours add nothing (the paper's sharpen,
-                              Section 4.2.4): FP32 filter2d_forward only
-                              (F2D_EUNSUPPORTED elsewhere) */
+                              Section 4.2.4): filter2d_forward on FP32 images and
+                              on U8 images in SHARED mode, and
+                              filter2d_upsample_forward (F2D_EUNSUPPORTED
+                              elsewhere) */
 
 /* channel modes */
 #define F2D_CH_SHARED 0
@@ -83,9 +86,13 @@ typedef int32_t f2d_status;
 
 /* A 4-D image [n][c][h][w]. */
 typedef struct f2d_tensor {
-  void* data;      /* device pointer to element (0,0,0,0) */
-  int32_t dtype;   /* F2D_U8 / F2D_I32 / F2D_F32 / F2D_BF16 */
-  int32_t reserved;
+  void* data;       /* device pointer to element (0,0,0,0) */
+  int32_t dtype;    /* F2D_U8 / F2D_I32 / F2D_F32 / F2D_BF16 */
+  int32_t stride_w; /* elements between horizontally adjacent pixels; 0 means 1.
+                       Planar layouts use 1; interleaved 8-bit images (OpenCV's
+                       pixel-after-pixel layout, Sections 4.2.3-4.2.4) use
+                       stride_w = c with stride_c = 1.  Only the 8-bit paths that
+                       say so accept a value other than 0 / 1. */
   int64_t n, c, h, w;
   int64_t stride_n, stride_c, stride_h; /* elements */
 } f2d_tensor;
@@ -124,14 +131,28 @@ typedef struct f2d_opts {
  *             BANK       n_outs = 1, C_o = f_out
  *   dtypes  U8 image + I32 filter -> I32 outputs (SHARED, DEPTHWISE): exact
  *           integer sums, wrapping modulo 2^32 if they leave the int32 range;
+ *           U8 image + F32 filter (the paper's float taps, Section 4.2.4) ->
+ *           F32 outputs: the sum in binary32, accumulator +0 and one fused
+ *           multiply-add per term (input channel, tap row, tap column);
+ *           U8 image + I32 or F32 filter -> U8 outputs: that sum clamped to
+ *           [0, 255] and rounded to nearest, ties to even (int32 sums are
+ *           clamped; they must stay inside the int32 range);
  *           F32 + F32 -> F32 (all modes), FP32 accumulation;
  *           BF16 + BF16 -> F32 or BF16 (BANK only), FP32 accumulation on the
  *           matrix cores, output rounded to nearest even for BF16.
  *   border  CLAMP for every dtype; ZERO for F32 images (all channel modes,
- *           bands included: rows outside the buffer read as 0).
- *   K       odd, 1 <= K <= 31 (F32, U8); K in {1,3,5} for BF16 banks (other
- *           odd K return F2D_EUNSUPPORTED); BF16 banks take at most 64 input
- *           channels.
+ *           bands included: rows outside the buffer read as 0) and for U8
+ *           images in SHARED mode.
+ *   U8      SHARED: K <= 7 unless the filter is I32 with I32 outputs, CLAMP
+ *           and a planar layout (then K <= 31); the image may be interleaved
+ *           (stride_c = 1, stride_w = C, C = 3 or 4) with an output in the same
+ *           layout.  DEPTHWISE: I32 taps and outputs, CLAMP, planar.  BANK:
+ *           K = 1 only (per-pixel channel mixing, e.g. the grayscale weights
+ *           of Section 4.2.5), at most 4 input and 4 output channels, planar
+ *           or interleaved input and output.
+ *   K       odd, 1 <= K <= 31 (F32, U8 as above); K in {1,3,5} for BF16 banks
+ *           (other odd K return F2D_EUNSUPPORTED); BF16 banks take at most 64
+ *           input channels.
  */
 f2d_status filter2d_forward(const f2d_tensor* image, const f2d_filter* filter,
                             const f2d_opts* opts, const f2d_tensor* outs, int32_t n_outs,
@@ -159,6 +180,27 @@ f2d_status filter2d_forward(const f2d_tensor* image, const f2d_filter* filter,
  */
 f2d_status filter2d_forward_separable(const f2d_tensor* image, const float* a, const float* b, int32_t k,
                                       const f2d_opts* opts, const f2d_tensor* out, void* stream);
+
+/*
+ * filter2d_upsample_forward -- the paper's upsample-then-sharpen pipeline
+ * (Section 6.6) in one pass: Y = filter(U), where U is X enlarged by nearest-
+ * neighbour upsampling by the integer factor `scale` (Section 4.2.3: output
+ * pixel (Y, X) copies source pixel (Y / scale, X / scale), integer division)
+ * and filter is filter2d_forward's SHARED map on U with opts->border (the
+ * border is U's border).  U is never written to memory: each output reads
+ * the source pixels its taps map to.
+ *
+ *   image   [N][C][H][W] U8, planar or interleaved (as filter2d_forward)
+ *   filter  [1][1][k][k], odd k <= 7, I32 or F32 taps
+ *   scale   >= 1 (1 is filter2d_forward)
+ *   opts    channels SHARED, epilogue NONE, whole images (row_begin = 0 and
+ *           row_end = 0 or H); border CLAMP or ZERO
+ *   out     [N][C][H*scale][W*scale] in the image's layout: U8 (clamped and
+ *           rounded as filter2d_forward), or I32 (I32 taps) / F32 (F32 taps)
+ * Ownership, validation and errors as for filter2d_forward.
+ */
+f2d_status filter2d_upsample_forward(const f2d_tensor* image, const f2d_filter* filter, int32_t scale,
+                                     const f2d_opts* opts, const f2d_tensor* out, void* stream);
 
 /*
  * Workspace bytes that filter2d_backward needs for these arguments (device

@@ -29,7 +29,7 @@ _DTYPES = {torch.uint8: U8, torch.int32: I32, torch.float32: F32, torch.bfloat16
 
 
 class F2dTensor(ctypes.Structure):
-    _fields_ = [("data", ctypes.c_void_p), ("dtype", ctypes.c_int32), ("reserved", ctypes.c_int32),
+    _fields_ = [("data", ctypes.c_void_p), ("dtype", ctypes.c_int32), ("stride_w", ctypes.c_int32),
                 ("n", ctypes.c_int64), ("c", ctypes.c_int64), ("h", ctypes.c_int64),
                 ("w", ctypes.c_int64), ("stride_n", ctypes.c_int64), ("stride_c", ctypes.c_int64),
                 ("stride_h", ctypes.c_int64)]
@@ -76,6 +76,7 @@ def load():
     sigs = {
         "filter2d_forward": (i32, [_P(F2dTensor), _P(F2dFilter), _P(F2dOpts), _P(F2dTensor), i32, vp]),
         "filter2d_forward_separable": (i32, [_P(F2dTensor), vp, vp, i32, _P(F2dOpts), _P(F2dTensor), vp]),
+        "filter2d_upsample_forward": (i32, [_P(F2dTensor), _P(F2dFilter), i32, _P(F2dOpts), _P(F2dTensor), vp]),
         "filter2d_backward_workspace": (sz, [_P(F2dTensor), _P(F2dFilter), _P(F2dOpts)]),
         "filter2d_backward": (i32, [_P(F2dTensor), _P(F2dFilter), _P(F2dTensor), i32, _P(F2dOpts),
                                     _P(F2dTensor), vp, vp, sz, vp]),
@@ -118,13 +119,15 @@ def _stream():
 
 
 def tensor_desc(t, dtype=None):
-    """Describe a 4-D [n][c][h][w] tensor (column stride must be 1)."""
+    """Describe a 4-D [n][c][h][w] tensor.  The column stride goes to
+    stride_w (1 for planar tensors; an interleaved [n][h][w][c] tensor viewed
+    with permute(0, 3, 1, 2) has stride_c 1 and stride_w c); the library
+    decides which paths accept it."""
     if t.dim() != 4:
         raise ValueError("expected a 4-D [n][c][h][w] tensor")
-    if t.size(3) > 1 and t.stride(3) != 1:
-        raise ValueError("the column (last) stride must be 1")
+    sw = t.stride(3) if t.size(3) > 1 else 1
     code = _DTYPES[t.dtype] if dtype is None else dtype
-    return F2dTensor(t.data_ptr(), code, 0, t.size(0), t.size(1), t.size(2), t.size(3),
+    return F2dTensor(t.data_ptr(), code, sw, t.size(0), t.size(1), t.size(2), t.size(3),
                      t.stride(0), t.stride(1), t.stride(2))
 
 
@@ -163,11 +166,33 @@ def out_count(mode, filt_shape, channels, epilogue):
     return 1
 
 
+def interleaved(t):
+    """True for an [n][c][h][w] view of interleaved [n][h][w][c] storage."""
+    return t.dim() == 4 and t.size(1) > 1 and t.stride(1) == 1 and t.stride(3) == t.size(1)
+
+
+def _new_out(image, filt, co, h, w, out_dtype, il):
+    if out_dtype is not None:
+        odt = out_dtype
+    elif image.dtype == torch.uint8:
+        odt = torch.int32 if filt.dtype == torch.int32 else torch.float32
+    else:
+        odt = torch.float32
+    n = image.size(0)
+    if il:
+        return torch.empty((n, h, w, co), dtype=odt, device=image.device).permute(0, 3, 1, 2)
+    return torch.empty((n, co, h, w), dtype=odt, device=image.device)
+
+
 def forward(image, filt, mode="shared", epilogue=EPI_NONE, rows=None, outs=None, variant=0,
             out_dtype=None, border="clamp"):
     """Y = filter(X) on the current stream.  Returns one tensor (SHARED, BANK)
     or the list of DEPTHWISE outputs (one per filter index, plus the SUMSQ one).
-    border: "clamp" (clamp-to-edge) or "zero" (FP32 images)."""
+    border: "clamp" (clamp-to-edge) or "zero".  u8 images: int32 taps give
+    int32 outputs and float taps float32 outputs unless out_dtype (e.g.
+    torch.uint8, clamped and rounded) says otherwise; an interleaved image
+    (an [n][h][w][c] tensor viewed with permute(0, 3, 1, 2)) gets outputs in
+    the same layout."""
     lib = load()
     image = _as4(image)
     fd, filt = filter_desc(filt)
@@ -176,18 +201,29 @@ def forward(image, filt, mode="shared", epilogue=EPI_NONE, rows=None, outs=None,
     r0, r1 = (0, h) if rows is None else rows
     nout = out_count(m, filt.shape, c, epilogue)
     if outs is None:
-        if image.dtype == torch.uint8:
-            odt = torch.int32
-        else:
-            odt = out_dtype or torch.float32
         co = filt.size(0) if m == BANK else c
-        outs = [torch.empty((n, co, r1 - r0, w), dtype=odt, device=image.device)
+        outs = [_new_out(image, filt, co, r1 - r0, w, out_dtype, interleaved(image) and m != BANK)
                 for _ in range(nout)]
     descs = (F2dTensor * len(outs))(*[tensor_desc(_as4(o)) for o in outs])
     opts = make_opts(m, epilogue, (r0, r1), variant, border)
     _check(lib.filter2d_forward(ctypes.byref(tensor_desc(image)), ctypes.byref(fd),
                                 ctypes.byref(opts), descs, len(outs), _stream()))
     return outs if m == DEPTHWISE else outs[0]
+
+
+def upsample_forward(image, filt, scale, out=None, out_dtype=None, border="clamp"):
+    """filter(nearest_upsample(image, scale)) in one pass (u8 images, SHARED):
+    returns [N][C][H*scale][W*scale] in the image's layout."""
+    lib = load()
+    image = _as4(image)
+    fd, filt = filter_desc(filt)
+    n, c, h, w = image.shape
+    if out is None:
+        out = _new_out(image, filt, c, h * scale, w * scale, out_dtype, interleaved(image))
+    opts = make_opts("shared", EPI_NONE, None, 0, border)
+    _check(lib.filter2d_upsample_forward(ctypes.byref(tensor_desc(image)), ctypes.byref(fd), int(scale),
+                                         ctypes.byref(opts), ctypes.byref(tensor_desc(_as4(out))), _stream()))
+    return out
 
 
 def forward_separable(image, a, b, rows=None, out=None):

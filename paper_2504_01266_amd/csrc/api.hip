@@ -140,12 +140,24 @@ f2d_status check_tensor(const f2d_tensor* t, const char* name, bool is_output) {
   if (!t) return fail(F2D_EINVAL, "%s: descriptor is NULL", name);
   if (t->n < 0 || t->c < 0 || t->h < 0 || t->w < 0)
     return fail(F2D_EINVAL, "%s: negative extent", name);
-  if (t->stride_n < 0 || t->stride_c < 0 || t->stride_h < 0)
+  if (t->stride_n < 0 || t->stride_c < 0 || t->stride_h < 0 || t->stride_w < 0)
     return fail(F2D_EINVAL, "%s: negative stride", name);
   if (t->dtype < F2D_U8 || t->dtype > F2D_BF16) return fail(F2D_EINVAL, "%s: unknown dtype %d", name, t->dtype);
   if (numel(*t) > 0 && !t->data) return fail(F2D_EINVAL, "%s: data is NULL", name);
   if (is_output && numel(*t) > 0) {
-    // outputs must not alias themselves: rows, planes and images disjoint
+    // outputs must not alias themselves
+    const int64_t sw = t->stride_w <= 1 ? 1 : t->stride_w;
+    if (sw > 1) {
+      // interleaved: channels inside the pixel, pixels inside the row, rows inside the image
+      const int64_t pixel = (t->c - 1) * t->stride_c + 1;
+      if (t->c > 1 && (t->stride_c < 1 || pixel > sw)) return fail(F2D_EINVAL, "%s: channels overlap", name);
+      const int64_t row = (t->w - 1) * sw + pixel;
+      if (t->h > 1 && t->stride_h < row) return fail(F2D_EINVAL, "%s: rows overlap", name);
+      const int64_t image = (t->h - 1) * t->stride_h + row;
+      if (t->n > 1 && t->stride_n < image) return fail(F2D_EINVAL, "%s: images overlap", name);
+      return F2D_OK;
+    }
+    // planar: rows, planes and images disjoint
     if (t->h > 1 && t->stride_h < t->w) return fail(F2D_EINVAL, "%s: stride_h < w", name);
     const int64_t plane = (t->h - 1) * t->stride_h + t->w;
     if (t->c > 1 && t->stride_c < plane) return fail(F2D_EINVAL, "%s: planes overlap", name);
@@ -224,9 +236,10 @@ f2d_status check_common(const f2d_tensor* image, const f2d_filter* filter, const
   // element-type combinations
   const int32_t it = image->dtype, ft = filter->dtype;
   if (it == F2D_U8) {
-    if (ft != F2D_I32) return fail(F2D_EINVAL, "u8 images need an int32 filter");
-    if (opts->channels == F2D_CH_BANK) return fail(F2D_EUNSUPPORTED, "u8 images: BANK mode is not implemented");
-    pr->out_dtype = F2D_I32;
+    if (ft != F2D_I32 && ft != F2D_F32) return fail(F2D_EINVAL, "u8 images need an int32 or float filter");
+    if (opts->channels == F2D_CH_BANK && k != 1)
+      return fail(F2D_EUNSUPPORTED, "u8 images in BANK mode: k = 1 (per-pixel channel mixing) only");
+    pr->out_dtype = ft == F2D_I32 ? F2D_I32 : F2D_F32;  // or U8, chosen by the output descriptor
   } else if (it == F2D_F32) {
     if (ft != F2D_F32) return fail(F2D_EINVAL, "f32 images need an f32 filter");
     if (opts->epilogue != F2D_EPI_NONE) return fail(F2D_EUNSUPPORTED, "SUMSQ_PAIRS is implemented for u8 images only");
@@ -239,8 +252,11 @@ f2d_status check_common(const f2d_tensor* image, const f2d_filter* filter, const
   } else {
     return fail(F2D_EUNSUPPORTED, "image dtype %d is not supported", it);
   }
-  if (opts->border == F2D_BORDER_ZERO && it != F2D_F32)
-    return fail(F2D_EUNSUPPORTED, "zero borders are implemented for f32 images only");
+  if (opts->border == F2D_BORDER_ZERO && it != F2D_F32 && it != F2D_U8)
+    return fail(F2D_EUNSUPPORTED, "zero borders are implemented for f32 and u8 images only");
+  if (it != F2D_U8 && image->stride_w > 1)
+    return fail(F2D_EUNSUPPORTED, "image stride_w %d: interleaved layouts are implemented for u8 images only",
+                image->stride_w);
   pr->image = *image;
   pr->filter = *filter;
   pr->opts = *opts;
@@ -266,8 +282,11 @@ f2d_status check_outputs(const Problem& pr, const f2d_tensor* outs, int32_t n_ou
                   static_cast<long long>(co), static_cast<long long>(pr.rows),
                   static_cast<long long>(pr.image.w));
     const bool bf16_ok = pr.image.dtype == F2D_BF16 && o.dtype == F2D_BF16;
-    if (o.dtype != pr.out_dtype && !bf16_ok)
+    const bool u8_ok = pr.image.dtype == F2D_U8 && o.dtype == F2D_U8;
+    if (o.dtype != pr.out_dtype && !bf16_ok && !u8_ok)
       return fail(F2D_EINVAL, "%s: dtype %d, expected %d", name, o.dtype, pr.out_dtype);
+    if (pr.image.dtype != F2D_U8 && o.stride_w > 1)
+      return fail(F2D_EUNSUPPORTED, "%s: interleaved layouts are implemented for u8 images only", name);
   }
   return F2D_OK;
 }
@@ -338,6 +357,27 @@ f2d_status filter2d_backward_noalloc(const f2d_tensor* image, const f2d_filter* 
     return fail(F2D_EUNSUPPORTED, "backward: clamp-to-edge borders only (zero borders are forward-only)");
   return run_backward_noalloc(pr, grad_outs, n_grad_outs, grad_input, grad_filter,
                               static_cast<hipStream_t>(stream));
+}
+
+f2d_status filter2d_upsample_forward(const f2d_tensor* image, const f2d_filter* filter, int32_t scale,
+                                     const f2d_opts* opts, const f2d_tensor* out, void* stream) {
+  Problem pr;
+  f2d_status s = check_common(image, filter, opts, &pr);
+  if (s) return s;
+  if (scale < 1) return fail(F2D_EINVAL, "upsample: scale %d < 1", scale);
+  if (image->dtype != F2D_U8) return fail(F2D_EUNSUPPORTED, "upsample: u8 images only");
+  if (opts->channels != F2D_CH_SHARED) return fail(F2D_EUNSUPPORTED, "upsample: SHARED channel mode only");
+  if (opts->epilogue != F2D_EPI_NONE) return fail(F2D_EINVAL, "upsample: no epilogue");
+  if (pr.row_begin != 0 || pr.row_end != image->h)
+    return fail(F2D_EUNSUPPORTED, "upsample: whole images only (row_begin = 0, row_end = 0 or h)");
+  if (!out) return fail(F2D_EINVAL, "upsample: out is NULL");
+  s = check_tensor(out, "out", true);
+  if (s) return s;
+  if (out->n != image->n || out->c != image->c || out->h != image->h * scale || out->w != image->w * scale)
+    return fail(F2D_EINVAL, "upsample: out must be [N][C][H*scale][W*scale]");
+  if (out->dtype != F2D_U8 && out->dtype != pr.out_dtype)
+    return fail(F2D_EINVAL, "upsample: out dtype %d (u8, or int32 for int32 taps, f32 for float taps)", out->dtype);
+  return run_upsample_forward(pr, scale, *out, static_cast<hipStream_t>(stream));
 }
 
 int64_t filter2d_batched_plan(const f2d_batch_item* items, int32_t n_items, int32_t dtype, int32_t k,

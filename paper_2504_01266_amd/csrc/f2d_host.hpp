@@ -47,6 +47,11 @@ f2d_status run_forward(const Problem& pr, const f2d_tensor* outs, int32_t n_outs
 f2d_status autotune_forward(const Problem& pr, const f2d_tensor* outs, int32_t n_outs, int32_t reps,
                             hipStream_t s, int32_t* best);
 
+// image_u8.hip: 8-bit images (zero borders, float taps, u8 outputs,
+// interleaved layouts, channel mixing, fused nearest upsampling)
+f2d_status forward_u8_image(const Problem& pr, const f2d_tensor* outs, int32_t n_outs, hipStream_t s);
+f2d_status run_upsample_forward(const Problem& pr, int32_t scale, const f2d_tensor& out, hipStream_t s);
+
 // separable_f32.hip (a, b: device pointers to k floats each)
 f2d_status run_forward_separable(const Problem& pr, const float* a, const float* b, const f2d_tensor& out,
                                  hipStream_t s);

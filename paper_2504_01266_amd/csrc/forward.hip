@@ -235,7 +235,14 @@ f2d_status run_forward(const Problem& pr, const f2d_tensor* outs, int32_t n_outs
     return ok();
   switch (pr.image.dtype) {
     case F2D_F32: return forward_f32(pr, outs, n_outs, s);
-    case F2D_U8: return forward_u8(pr, outs, n_outs, s);
+    case F2D_U8: {
+      // the integer Sobel path: int32 taps and outputs, clamp-to-edge, planar
+      bool int_path = pr.filter.dtype == F2D_I32 && pr.opts.border == F2D_BORDER_CLAMP &&
+                      pr.mode != F2D_CH_BANK && pr.image.stride_w <= 1;
+      for (int32_t j = 0; j < n_outs; ++j) int_path = int_path && outs[j].dtype == F2D_I32 && outs[j].stride_w <= 1;
+      if (int_path) return forward_u8(pr, outs, n_outs, s);
+      return forward_u8_image(pr, outs, n_outs, s);
+    }
     case F2D_BF16: return bank_forward_bf16(pr, outs, s);
     default: return fail(F2D_EUNSUPPORTED, "image dtype %d", pr.image.dtype);
   }

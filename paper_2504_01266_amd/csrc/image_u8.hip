@@ -1,0 +1,521 @@
+// 8-bit image kernels: the paper's own image operations on its own data type.
+//
+// The paper filters 8-bit images read with OpenCV (interleaved channels, one
+// pixel after another) with float taps: a 3x3 Laplacian sharpen that skips
+// out-of-image neighbours (Section 4.2.4), run on images enlarged by nearest-
+// neighbour upsampling (Section 4.2.3; the pipeline of Section 6.6), and a
+// weighted RGB -> gray sum (Section 4.2.5).  Two kernels cover them:
+//
+//  k_u8_gather  one K x K filter (SHARED mode) on planar or interleaved 8-bit
+//               images, clamp-to-edge or zero borders, optionally through a
+//               nearest upsample by an integer factor s (output pixel (Y, X)
+//               reads source pixel (Y / s, X / s)) that is never materialised.
+//               A work-group owns a 32-row x 2048-element output tile (an
+//               element is one channel of one pixel: for interleaved images a
+//               row is W*s*C elements long and the tap offsets step C
+//               elements).  It first stages the source rows the tile needs,
+//               already expanded along the row (window element j holds the
+//               source byte for output element e0 - rC + j, or 0 outside a
+//               zero border) into LDS.  Each lane then walks down the tile's
+//               rows producing 8 consecutive elements per row from its window
+//               of 8 + 2rC bytes.  Rows whose K source rows are the same as the
+//               previous row's (inside an upsampled block when s > 1) reuse
+//               the previous values and only store.
+//  k_u8_mix     per-pixel channel mixing (BANK mode with K = 1, e.g. the
+//               grayscale weights): up to 4 input and 4 output channels,
+//               planar or interleaved, four pixels per lane.
+//
+// Arithmetic.  Float taps: binary32, accumulator +0, one fused multiply-add
+// per term in the order input channel, tap row, tap column.  Integer taps:
+// int32 sums (wrapping modulo 2^32).  8-bit outputs: the sum is clamped to
+// [0, 255] and rounded to nearest, ties to even.
+#include <hip/hip_runtime.h>
+
+#include <cstring>
+
+#include "f2d_host.hpp"
+#include "f2d_internal.hpp"
+
+namespace f2d {
+namespace {
+
+constexpr int kOutI32 = 0;
+constexpr int kOutF32 = 1;
+constexpr int kOutU8 = 2;
+
+constexpr int kGThreads = 256;
+constexpr int kGElems = 8;                   // output elements per lane and row
+constexpr int kGTW = kGThreads * kGElems;    // 2048 elements per tile row
+constexpr int kGTH = 32;                     // output rows per tile
+constexpr int kGPitchWords = (kGTW + 32) / 4;  // staged row: 2048 + 2rC (<= 2072) bytes + read slack
+
+struct GatherParams {
+  const uint8_t* src;  // element (n, c, 0, 0): planar planes, or interleaved rows (stride_c 1)
+  int64_t s_sn, s_sc, s_sh;
+  void* dst;  // same layout as the source, in elements of the output type
+  int64_t d_sn, d_sc, d_sh;
+  const void* taps;  // K*K int32 or float
+  int64_t H, W;      // source image, pixels
+  int64_t Hout, Wout;  // H*s, W*s
+  int64_t row0, out_rows;  // output rows [row0, row0 + out_rows) of the (upsampled) buffer
+  int32_t s;         // nearest-upsample factor
+  int32_t zero;      // zero borders (else clamp-to-edge)
+  int32_t planes_c;  // planes per image on the grid: C (planar) or 1 (interleaved)
+  int32_t tiles_x, tiles_y;
+  int64_t n_blocks;
+  int32_t vec;  // output rows aligned for the lanes' vector stores
+};
+
+template <int K, int P, bool TF, int OUT>
+__global__ __launch_bounds__(kGThreads) void k_u8_gather(GatherParams p) {
+  constexpr int R = (K - 1) / 2;
+  constexpr int RP = R * P;
+  constexpr int WIN = kGTW + 2 * RP;          // staged elements per row
+  constexpr int WORDS = (WIN + 3) / 4;
+  constexpr int NW = (kGElems + 2 * RP + 3) / 4;  // words of a lane's window
+  constexpr int MAXROWS = kGTH + 2 * R;       // distinct source rows of a tile (s = 1)
+  constexpr int ZROW = MAXROWS;              // an all-zero row for zero borders
+  static_assert(WORDS <= kGPitchWords && 2 * (kGThreads - 1) + NW <= kGPitchWords, "staged row too short");
+  __shared__ uint32_t lds[(MAXROWS + 1) * kGPitchWords];
+  using Acc = typename std::conditional<TF, float, uint32_t>::type;
+
+  const int tid = threadIdx.x;
+  const int64_t b = xcd_remap(blockIdx.x, p.n_blocks);
+  const int64_t tiles = static_cast<int64_t>(p.tiles_x) * p.tiles_y;
+  const int64_t plane = b / tiles;
+  const int64_t t_in = b - plane * tiles;
+  const int64_t ty = t_in / p.tiles_x;
+  const int64_t tx = t_in - ty * p.tiles_x;
+  const int64_t n = plane / p.planes_c;
+  const int64_t c = plane - n * p.planes_c;
+  const uint8_t* sp = p.src + n * p.s_sn + c * p.s_sc;
+  const int64_t e0 = tx * kGTW;               // first output element of the tile
+  const int64_t y0 = ty * kGTH;               // first output row (band-relative)
+  const int64_t L = p.Wout * P;               // elements per output row
+  const int64_t s = p.s;
+  const int64_t nrow_out = min(static_cast<int64_t>(kGTH), p.out_rows - y0);
+
+  // source rows the tile reads: the upsampled rows t = row0 + y + u - R,
+  // clamped to [0, Hout) (zero-border rows outside are the zero row)
+  auto clamp_out_row = [&](int64_t t) { return t < 0 ? int64_t{0} : (t >= p.Hout ? p.Hout - 1 : t); };
+  const int64_t rlo = clamp_out_row(p.row0 + y0 - R) / s;
+  const int64_t rhi = clamp_out_row(p.row0 + y0 + nrow_out - 1 + R) / s;
+  const int nsrc = static_cast<int>(rhi - rlo + 1);
+
+  // ---- stage: row-expanded source bytes of every source row of the tile
+  // (element and pixel indices fit in 32 bits: rows of at most 2^30 elements)
+  const uint32_t s32 = static_cast<uint32_t>(p.s);
+  const int32_t wout = static_cast<int32_t>(p.Wout);
+  for (int q = tid; q < WORDS; q += kGThreads) {
+    int32_t off[4];
+#pragma unroll
+    for (int jj = 0; jj < 4; ++jj) {
+      const int32_t e = static_cast<int32_t>(e0) - RP + 4 * q + jj;  // >= -RP
+      const int32_t xu = (e + P * 4) / P - 4;                      // floor(e / P)
+      const int32_t ch = e - xu * P;
+      int32_t xc = xu;
+      bool inside = xu >= 0 && xu < wout;
+      if (!inside && !p.zero) {
+        xc = xu < 0 ? 0 : wout - 1;
+        inside = true;
+      }
+      off[jj] = inside ? static_cast<int32_t>(static_cast<uint32_t>(xc) / s32) * P + ch : -1;
+    }
+    for (int ri = 0; ri < nsrc; ++ri) {
+      const uint8_t* rp = sp + (rlo + ri) * p.s_sh;
+      uint32_t w = 0;
+#pragma unroll
+      for (int jj = 0; jj < 4; ++jj)
+        if (off[jj] >= 0) w |= static_cast<uint32_t>(rp[off[jj]]) << (8 * jj);
+      lds[ri * kGPitchWords + q] = w;
+    }
+    lds[ZROW * kGPitchWords + q] = 0u;
+  }
+  __syncthreads();
+
+  // ---- taps (uniform)
+  Acc tap[K * K];
+#pragma unroll
+  for (int i = 0; i < K * K; ++i) tap[i] = static_cast<const Acc*>(p.taps)[i];
+
+  // ---- walk the rows
+  int32_t prev[K];
+#pragma unroll
+  for (int u = 0; u < K; ++u) prev[u] = -1;
+  uint32_t outw[OUT == kOutU8 ? 2 : kGElems];
+  const int64_t ebase = e0 + kGElems * tid;
+  for (int64_t i = 0; i < nrow_out; ++i) {
+    const int64_t y = y0 + i;
+    int32_t ridx[K];
+    bool same = i > 0;
+#pragma unroll
+    for (int u = 0; u < K; ++u) {
+      const int64_t t = p.row0 + y + u - R;
+      int32_t r;
+      if ((t < 0 || t >= p.Hout) && p.zero)
+        r = ZROW;
+      else
+        r = static_cast<int32_t>(static_cast<uint32_t>(clamp_out_row(t)) / s32 - static_cast<uint32_t>(rlo));
+      ridx[u] = r;
+      same = same && r == prev[u];
+      prev[u] = r;
+    }
+    if (!same) {
+      Acc acc[kGElems];
+#pragma unroll
+      for (int j = 0; j < kGElems; ++j) acc[j] = Acc(0);
+#pragma unroll
+      for (int u = 0; u < K; ++u) {
+        const uint32_t* row = lds + ridx[u] * kGPitchWords + 2 * tid;
+        uint32_t w[NW];
+#pragma unroll
+        for (int k2 = 0; k2 < NW; ++k2) w[k2] = row[k2];
+#pragma unroll
+        for (int v = 0; v < K; ++v)
+#pragma unroll
+          for (int j = 0; j < kGElems; ++j) {
+            const int bi = j + v * P;
+            const uint32_t byte = (w[bi >> 2] >> (8 * (bi & 3))) & 0xffu;
+            if constexpr (TF)
+              acc[j] = __builtin_fmaf(tap[u * K + v], static_cast<float>(byte), acc[j]);
+            else
+              acc[j] += byte * tap[u * K + v];
+          }
+      }
+      if constexpr (OUT == kOutU8) {
+        uint32_t q8[kGElems];
+#pragma unroll
+        for (int j = 0; j < kGElems; ++j) {
+          if constexpr (TF) {
+            const float v = __builtin_rintf(__builtin_amdgcn_fmed3f(acc[j], 0.0f, 255.0f));
+            q8[j] = static_cast<uint32_t>(v);
+          } else {
+            const int32_t v = static_cast<int32_t>(acc[j]);
+            q8[j] = static_cast<uint32_t>(v < 0 ? 0 : (v > 255 ? 255 : v));
+          }
+        }
+        outw[0] = q8[0] | (q8[1] << 8) | (q8[2] << 16) | (q8[3] << 24);
+        outw[1] = q8[4] | (q8[5] << 8) | (q8[6] << 16) | (q8[7] << 24);
+      } else {
+#pragma unroll
+        for (int j = 0; j < kGElems; ++j) outw[j] = __builtin_bit_cast(uint32_t, acc[j]);
+      }
+    }
+    // ---- store the lane's 8 elements of row y
+    if (ebase < L) {
+      if constexpr (OUT == kOutU8) {
+        uint8_t* dp = static_cast<uint8_t*>(p.dst) + n * p.d_sn + c * p.d_sc + y * p.d_sh + ebase;
+        if (p.vec && ebase + kGElems <= L) {
+          *reinterpret_cast<uint2*>(dp) = make_uint2(outw[0], outw[1]);
+        } else {
+#pragma unroll
+          for (int j = 0; j < kGElems; ++j)
+            if (ebase + j < L) dp[j] = static_cast<uint8_t>(outw[j >> 2] >> (8 * (j & 3)));
+        }
+      } else {
+        uint32_t* dp = static_cast<uint32_t*>(p.dst) + n * p.d_sn + c * p.d_sc + y * p.d_sh + ebase;
+        if (p.vec && ebase + kGElems <= L) {
+          reinterpret_cast<uint4*>(dp)[0] = make_uint4(outw[0], outw[1], outw[2], outw[3]);
+          reinterpret_cast<uint4*>(dp)[1] = make_uint4(outw[4], outw[5], outw[6], outw[7]);
+        } else {
+#pragma unroll
+          for (int j = 0; j < kGElems; ++j)
+            if (ebase + j < L) dp[j] = outw[j];
+        }
+      }
+    }
+  }
+}
+
+// ------------------------------------------------------------- channel mix --
+
+struct MixParams {
+  const uint8_t* src;
+  int64_t s_sn, s_sc, s_sh, s_sw;  // elements; interleaved: s_sc = 1, s_sw = CIN
+  void* dst;
+  int64_t d_sn, d_sc, d_sh, d_sw;  // elements of the output type
+  const void* w;                   // [cout][CIN], int32 or float
+  int32_t cout;
+  int64_t W, row0, rows;  // output rows [row0, row0 + rows) of the buffer
+  int32_t tiles_x;        // 1024-pixel segments per row
+  int64_t n_blocks;
+  int32_t in_vec;   // source rows word-aligned (planar) / interleaved rows word-aligned
+  int32_t out_vec;  // output planes rows aligned for 4-pixel stores (planar output)
+};
+
+constexpr int kMixThreads = 256;
+constexpr int kMixPx = 4;  // pixels per lane
+
+template <int CIN, bool TF, int OUT>
+__global__ __launch_bounds__(kMixThreads) void k_u8_mix(MixParams p) {
+  using Acc = typename std::conditional<TF, float, uint32_t>::type;
+  const int64_t b = xcd_remap(blockIdx.x, p.n_blocks);
+  const int64_t per_img = p.rows * p.tiles_x;
+  const int64_t n = b / per_img;
+  const int64_t rem = b - n * per_img;
+  const int64_t y = rem / p.tiles_x;
+  const int64_t x0 = (rem - y * p.tiles_x) * (kMixThreads * kMixPx) + kMixPx * threadIdx.x;
+  if (x0 >= p.W) return;
+  const bool full = x0 + kMixPx <= p.W;
+  const uint8_t* rp = p.src + n * p.s_sn + (p.row0 + y) * p.s_sh;
+
+  // x[i][k]: channel i of pixel x0 + k
+  uint32_t x[CIN][kMixPx];
+  if (p.s_sw == CIN && p.s_sc == 1 && CIN > 1) {  // interleaved
+    if (p.in_vec && full) {
+      uint32_t wd[CIN];
+#pragma unroll
+      for (int q = 0; q < CIN; ++q) wd[q] = reinterpret_cast<const uint32_t*>(rp + x0 * CIN)[q];
+#pragma unroll
+      for (int k = 0; k < kMixPx; ++k)
+#pragma unroll
+        for (int i = 0; i < CIN; ++i) {
+          const int bi = k * CIN + i;
+          x[i][k] = (wd[bi >> 2] >> (8 * (bi & 3))) & 0xffu;
+        }
+    } else {
+#pragma unroll
+      for (int k = 0; k < kMixPx; ++k)
+#pragma unroll
+        for (int i = 0; i < CIN; ++i) x[i][k] = x0 + k < p.W ? rp[(x0 + k) * CIN + i] : 0u;
+    }
+  } else {  // planar
+#pragma unroll
+    for (int i = 0; i < CIN; ++i) {
+      const uint8_t* cp = rp + i * p.s_sc;
+      if (p.in_vec && full) {
+        const uint32_t wd = *reinterpret_cast<const uint32_t*>(cp + x0);
+#pragma unroll
+        for (int k = 0; k < kMixPx; ++k) x[i][k] = (wd >> (8 * k)) & 0xffu;
+      } else {
+#pragma unroll
+        for (int k = 0; k < kMixPx; ++k) x[i][k] = x0 + k < p.W ? cp[(x0 + k) * p.s_sw] : 0u;
+      }
+    }
+  }
+
+  const Acc* w = static_cast<const Acc*>(p.w);
+#pragma unroll
+  for (int o = 0; o < 4; ++o) {
+    if (o >= p.cout) break;
+    Acc acc[kMixPx];
+#pragma unroll
+    for (int k = 0; k < kMixPx; ++k) acc[k] = Acc(0);
+#pragma unroll
+    for (int i = 0; i < CIN; ++i) {
+      const Acc wi = w[o * CIN + i];
+#pragma unroll
+      for (int k = 0; k < kMixPx; ++k) {
+        if constexpr (TF)
+          acc[k] = __builtin_fmaf(wi, static_cast<float>(x[i][k]), acc[k]);
+        else
+          acc[k] += x[i][k] * wi;
+      }
+    }
+    const int64_t obase = n * p.d_sn + o * p.d_sc + (y)*p.d_sh;
+    if constexpr (OUT == kOutU8) {
+      uint32_t q8[kMixPx];
+#pragma unroll
+      for (int k = 0; k < kMixPx; ++k) {
+        if constexpr (TF) {
+          q8[k] = static_cast<uint32_t>(__builtin_rintf(__builtin_amdgcn_fmed3f(acc[k], 0.0f, 255.0f)));
+        } else {
+          const int32_t v = static_cast<int32_t>(acc[k]);
+          q8[k] = static_cast<uint32_t>(v < 0 ? 0 : (v > 255 ? 255 : v));
+        }
+      }
+      uint8_t* dp = static_cast<uint8_t*>(p.dst) + obase;
+      if (p.out_vec && full && p.d_sw == 1) {
+        *reinterpret_cast<uint32_t*>(dp + x0) = q8[0] | (q8[1] << 8) | (q8[2] << 16) | (q8[3] << 24);
+      } else {
+#pragma unroll
+        for (int k = 0; k < kMixPx; ++k)
+          if (x0 + k < p.W) dp[(x0 + k) * p.d_sw] = static_cast<uint8_t>(q8[k]);
+      }
+    } else {
+      uint32_t* dp = static_cast<uint32_t*>(p.dst) + obase;
+      if (p.out_vec && full && p.d_sw == 1) {
+        *reinterpret_cast<uint4*>(dp + x0) =
+            make_uint4(__builtin_bit_cast(uint32_t, acc[0]), __builtin_bit_cast(uint32_t, acc[1]),
+                       __builtin_bit_cast(uint32_t, acc[2]), __builtin_bit_cast(uint32_t, acc[3]));
+      } else {
+#pragma unroll
+        for (int k = 0; k < kMixPx; ++k)
+          if (x0 + k < p.W) dp[(x0 + k) * p.d_sw] = __builtin_bit_cast(uint32_t, acc[k]);
+      }
+    }
+  }
+}
+
+// ------------------------------------------------------------------ host ----
+
+int64_t eff_sw(const f2d_tensor& t) { return t.stride_w <= 0 ? 1 : t.stride_w; }
+
+// Interleaved: channels adjacent (stride_c 1) and pixels C apart, C > 1.
+bool interleaved(const f2d_tensor& t) { return t.c > 1 && t.stride_c == 1 && eff_sw(t) == t.c; }
+
+// Row starts aligned to `bytes` (base pointer, row and image strides); the
+// channel stride is ignored for interleaved tensors, whose channels sit
+// inside the pixel.
+bool rows_aligned(const f2d_tensor& t, size_t bytes) {
+  if (!interleaved(t)) return row_aligned(t, bytes);
+  const size_t es = t.dtype == F2D_U8 ? 1 : 4;
+  const uintptr_t a = reinterpret_cast<uintptr_t>(t.data);
+  return a % bytes == 0 && (t.h <= 1 || (t.stride_h * es) % bytes == 0) &&
+         (t.n <= 1 || (t.stride_n * es) % bytes == 0);
+}
+
+template <int K, int P>
+hipError_t launch_gather_kp(const GatherParams& g, bool tf, int out, hipStream_t s) {
+  const dim3 grid(static_cast<uint32_t>(g.n_blocks)), block(kGThreads);
+  if (tf) {
+    if (out == kOutU8) hipLaunchKernelGGL((k_u8_gather<K, P, true, kOutU8>), grid, block, 0, s, g);
+    else hipLaunchKernelGGL((k_u8_gather<K, P, true, kOutF32>), grid, block, 0, s, g);
+  } else {
+    if (out == kOutU8) hipLaunchKernelGGL((k_u8_gather<K, P, false, kOutU8>), grid, block, 0, s, g);
+    else hipLaunchKernelGGL((k_u8_gather<K, P, false, kOutI32>), grid, block, 0, s, g);
+  }
+  return hipGetLastError();
+}
+
+template <int K>
+hipError_t launch_gather_k(const GatherParams& g, int P, bool tf, int out, hipStream_t s) {
+  switch (P) {
+    case 1: return launch_gather_kp<K, 1>(g, tf, out, s);
+    case 3: return launch_gather_kp<K, 3>(g, tf, out, s);
+    default: return launch_gather_kp<K, 4>(g, tf, out, s);
+  }
+}
+
+int out_kind(int32_t dtype) { return dtype == F2D_U8 ? kOutU8 : (dtype == F2D_F32 ? kOutF32 : kOutI32); }
+
+// SHARED filter on an 8-bit image, optional nearest upsample by `scale`.
+f2d_status gather_forward(const Problem& pr, const f2d_tensor& out, int32_t scale, hipStream_t s) {
+  const f2d_tensor& im = pr.image;
+  const bool il = interleaved(im);
+  if (!il && eff_sw(im) != 1) return fail(F2D_EUNSUPPORTED, "u8 images: planar or interleaved (stride_c 1, stride_w C) layouts");
+  const int P = il ? static_cast<int>(im.c) : 1;
+  if (il && P != 3 && P != 4) return fail(F2D_EUNSUPPORTED, "interleaved u8 images: 3 or 4 channels");
+  if (il != interleaved(out) || (!il && eff_sw(out) != 1))
+    return fail(F2D_EINVAL, "the output must have the image's layout (planar, or interleaved with the same channels)");
+  if (pr.k > 7) return fail(F2D_EUNSUPPORTED, "u8 zero-border / u8-output / float-tap / upsampled filters: k <= 7 (got %d)", pr.k);
+  const bool tf = pr.filter.dtype == F2D_F32;
+  const int ok_out = out_kind(out.dtype);
+  if ((tf && ok_out == kOutI32) || (!tf && ok_out == kOutF32))
+    return fail(F2D_EINVAL, "u8 images: int32 taps give int32 or u8 outputs, float taps give f32 or u8 outputs");
+  GatherParams g;
+  std::memset(&g, 0, sizeof(g));
+  g.src = static_cast<const uint8_t*>(im.data);
+  g.s_sn = im.stride_n;
+  g.s_sc = il ? 0 : im.stride_c;
+  g.s_sh = im.stride_h;
+  g.dst = out.data;
+  g.d_sn = out.stride_n;
+  g.d_sc = il ? 0 : out.stride_c;
+  g.d_sh = out.stride_h;
+  g.taps = pr.filter.data;
+  g.H = im.h;
+  g.W = im.w;
+  g.s = scale;
+  g.Hout = im.h * scale;
+  g.Wout = im.w * scale;
+  g.row0 = pr.row_begin;
+  g.out_rows = scale == 1 ? pr.rows : g.Hout;
+  g.zero = pr.opts.border == F2D_BORDER_ZERO ? 1 : 0;
+  g.planes_c = il ? 1 : static_cast<int32_t>(im.c);
+  const int64_t L = g.Wout * P;
+  if (L > (int64_t{1} << 30) || g.Hout > (int64_t{1} << 30))
+    return fail(F2D_EUNSUPPORTED, "u8 filter: output rows of at most 2^30 elements and 2^30 rows");
+  g.tiles_x = static_cast<int32_t>((L + kGTW - 1) / kGTW);
+  g.tiles_y = static_cast<int32_t>((g.out_rows + kGTH - 1) / kGTH);
+  g.n_blocks = im.n * g.planes_c * static_cast<int64_t>(g.tiles_x) * g.tiles_y;
+  if (g.n_blocks > kMaxBlocks) return fail(F2D_EUNSUPPORTED, "u8 filter: too many tiles for one launch");
+  g.vec = rows_aligned(out, ok_out == kOutU8 ? 8 : 16) ? 1 : 0;
+  if (g.n_blocks == 0) return ok();
+  hipError_t e;
+  switch (pr.k) {
+    case 1: e = launch_gather_k<1>(g, P, tf, ok_out, s); break;
+    case 3: e = launch_gather_k<3>(g, P, tf, ok_out, s); break;
+    case 5: e = launch_gather_k<5>(g, P, tf, ok_out, s); break;
+    default: e = launch_gather_k<7>(g, P, tf, ok_out, s); break;
+  }
+  return hip_status(e, "u8 filter launch");
+}
+
+template <int CIN>
+hipError_t launch_mix_c(const MixParams& m, bool tf, int out, hipStream_t s) {
+  const dim3 grid(static_cast<uint32_t>(m.n_blocks)), block(kMixThreads);
+  if (tf) {
+    if (out == kOutU8) hipLaunchKernelGGL((k_u8_mix<CIN, true, kOutU8>), grid, block, 0, s, m);
+    else hipLaunchKernelGGL((k_u8_mix<CIN, true, kOutF32>), grid, block, 0, s, m);
+  } else {
+    if (out == kOutU8) hipLaunchKernelGGL((k_u8_mix<CIN, false, kOutU8>), grid, block, 0, s, m);
+    else hipLaunchKernelGGL((k_u8_mix<CIN, false, kOutI32>), grid, block, 0, s, m);
+  }
+  return hipGetLastError();
+}
+
+// BANK with K = 1 on an 8-bit image: per-pixel channel mixing.
+f2d_status mix_forward(const Problem& pr, const f2d_tensor& out, hipStream_t s) {
+  const f2d_tensor& im = pr.image;
+  if (pr.k != 1) return fail(F2D_EUNSUPPORTED, "u8 images in BANK mode: k = 1 (per-pixel channel mixing) only");
+  if (im.c > 4 || pr.c_out > 4) return fail(F2D_EUNSUPPORTED, "u8 channel mixing: at most 4 input and 4 output channels");
+  const bool il = interleaved(im);
+  if (!il && eff_sw(im) != 1) return fail(F2D_EUNSUPPORTED, "u8 images: planar or interleaved layouts");
+  const bool oil = interleaved(out);
+  if (!oil && eff_sw(out) != 1) return fail(F2D_EUNSUPPORTED, "u8 channel mixing: planar or interleaved outputs");
+  const bool tf = pr.filter.dtype == F2D_F32;
+  const int ok_out = out_kind(out.dtype);
+  if ((tf && ok_out == kOutI32) || (!tf && ok_out == kOutF32))
+    return fail(F2D_EINVAL, "u8 images: int32 weights give int32 or u8 outputs, float weights give f32 or u8 outputs");
+  MixParams m;
+  std::memset(&m, 0, sizeof(m));
+  m.src = static_cast<const uint8_t*>(im.data);
+  m.s_sn = im.stride_n;
+  m.s_sc = im.stride_c;
+  m.s_sh = im.stride_h;
+  m.s_sw = eff_sw(im);
+  m.dst = out.data;
+  m.d_sn = out.stride_n;
+  m.d_sc = out.stride_c;
+  m.d_sh = out.stride_h;
+  m.d_sw = eff_sw(out);
+  m.w = pr.filter.data;
+  m.cout = static_cast<int32_t>(pr.c_out);
+  m.W = im.w;
+  m.row0 = pr.row_begin;
+  m.rows = pr.rows;
+  m.tiles_x = static_cast<int32_t>((im.w + kMixThreads * kMixPx - 1) / (kMixThreads * kMixPx));
+  m.n_blocks = im.n * m.rows * m.tiles_x;
+  if (m.n_blocks > kMaxBlocks) return fail(F2D_EUNSUPPORTED, "u8 channel mixing: too many tiles for one launch");
+  m.in_vec = rows_aligned(im, 4) ? 1 : 0;
+  m.out_vec = !oil && row_aligned(out, ok_out == kOutU8 ? 4 : 16) ? 1 : 0;
+  if (m.n_blocks == 0) return ok();
+  hipError_t e;
+  switch (im.c) {
+    case 1: e = launch_mix_c<1>(m, tf, ok_out, s); break;
+    case 2: e = launch_mix_c<2>(m, tf, ok_out, s); break;
+    case 3: e = launch_mix_c<3>(m, tf, ok_out, s); break;
+    default: e = launch_mix_c<4>(m, tf, ok_out, s); break;
+  }
+  return hip_status(e, "u8 channel mixing launch");
+}
+
+}  // namespace
+
+// 8-bit images beyond the integer Sobel path: zero borders, float taps, u8
+// outputs, interleaved layouts (SHARED), and channel mixing (BANK, K = 1).
+f2d_status forward_u8_image(const Problem& pr, const f2d_tensor* outs, int32_t n_outs, hipStream_t s) {
+  if (pr.mode == F2D_CH_DEPTHWISE)
+    return fail(F2D_EUNSUPPORTED, "u8 DEPTHWISE filters: int32 taps, int32 outputs, clamp borders, planar layout");
+  if (n_outs != 1) return fail(F2D_EINVAL, "expected one output");
+  if (pr.mode == F2D_CH_BANK) return mix_forward(pr, outs[0], s);
+  return gather_forward(pr, outs[0], 1, s);
+}
+
+f2d_status run_upsample_forward(const Problem& pr, int32_t scale, const f2d_tensor& out, hipStream_t s) {
+  if (pr.image.n == 0 || pr.image.h == 0 || pr.image.w == 0 || pr.image.c == 0) return ok();
+  return gather_forward(pr, out, scale, s);
+}
+
+}  // namespace f2d

@@ -129,6 +129,12 @@ def sharpen_frame(h=2160, w=3840, c=3):
     return rng(9, 4, h, w).integers(0, 256, (1, c, h, w)).astype(np.float32)
 
 
+def paper_frame_u8(h=2160, w=3840, c=3, seed=10):
+    """A 4K RGB frame as OpenCV delivers it (Sections 4.2.3-4.2.5): 8-bit
+    values uniform in [0, 255], interleaved [H][W][C] (pixel after pixel)."""
+    return rng(seed, 1, h, w).integers(0, 256, (h, w, c), dtype=np.uint8)
+
+
 def diff_image(n, c=3, h=2048, w=2048):
     return rng(DIFF_SEED, 1, n).random((c, h, w), dtype=np.float32)
 

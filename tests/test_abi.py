@@ -78,8 +78,28 @@ CASES = [
      [_img()], B.EINVAL, "multiple"),
     ("bank f_in != C", _img(c=3), _filt(f_out=4, f_in=2), B.make_opts("bank"), [_img()], B.EINVAL,
      "f_in"),
-    ("zero border on u8", _img(B.U8), _filt(dtype=B.I32), B.F2dOpts(B.BORDER_ZERO, 0, 0, 0, 0, 0),
-     [_img(B.I32)], B.EUNSUPPORTED, "f32 images only"),
+    ("zero border on bf16", _img(B.BF16), _filt(f_out=4, f_in=3, dtype=B.BF16),
+     B.F2dOpts(B.BORDER_ZERO, B.BANK, 0, 0, 0, 0), [_img(c=4)], B.EUNSUPPORTED, "f32 and u8 images only"),
+    ("zero border on u8 depthwise", _img(B.U8), _filt(f_out=6, dtype=B.I32),
+     B.F2dOpts(B.BORDER_ZERO, B.DEPTHWISE, 0, 0, 0, 0), [_img(B.I32), _img(B.I32)], B.EUNSUPPORTED,
+     "DEPTHWISE"),
+    ("u8 bank k > 1", _img(B.U8), _filt(f_out=1, f_in=3, dtype=B.F32), B.make_opts("bank"),
+     [_img(B.U8, c=1)], B.EUNSUPPORTED, "k = 1"),
+    ("u8 bank more than 4 channels", _img(B.U8, c=5), _filt(k=1, f_out=1, f_in=5, dtype=B.F32),
+     B.make_opts("bank"), [_img(B.U8, c=1)], B.EUNSUPPORTED, "at most 4"),
+    ("u8 shared float taps k > 7", _img(B.U8), _filt(k=9, dtype=B.F32), B.make_opts(), [_img(B.U8)],
+     B.EUNSUPPORTED, "k <= 7"),
+    ("u8 int taps with f32 outputs", _img(B.U8), _filt(dtype=B.I32), B.make_opts(border="zero"),
+     [_img(B.F32)], B.EINVAL, "dtype"),
+    ("u8 float taps with i32 outputs", _img(B.U8), _filt(dtype=B.F32), B.make_opts(), [_img(B.I32)],
+     B.EINVAL, "dtype"),
+    ("interleaved f32 image", B.F2dTensor(FAKE, B.F32, 3, 1, 3, 32, 40, 3840, 1, 120), _filt(),
+     B.make_opts(), [_img()], B.EUNSUPPORTED, "u8 images only"),
+    ("interleaved u8 in, planar out", B.F2dTensor(FAKE, B.U8, 3, 1, 3, 32, 40, 3840, 1, 120),
+     _filt(dtype=B.F32), B.make_opts(), [_img(B.U8)], B.EINVAL, "layout"),
+    ("interleaved output channels overlap", B.F2dTensor(FAKE, B.U8, 3, 1, 3, 32, 40, 3840, 1, 120),
+     _filt(dtype=B.F32), B.make_opts(), [B.F2dTensor(FAKE, B.U8, 2, 1, 3, 32, 40, 3840, 1, 80)],
+     B.EINVAL, "channels overlap"),
     ("unknown border", _img(), _filt(), B.F2dOpts(7, 0, 0, 0, 0, 0), [_img()], B.EINVAL, "border"),
     ("wrong output count", _img(), _filt(), B.make_opts(), [_img(), _img()], B.EINVAL, "expected 1"),
     ("wrong output shape", _img(), _filt(), B.make_opts(), [_img(h=31)], B.EINVAL, "shape"),
@@ -91,7 +111,8 @@ CASES = [
      [B.F2dTensor(None, B.F32, 0, 1, 3, 32, 40, 3840, 1280, 40)], B.EINVAL, "NULL"),
     ("overlapping output rows", _img(), _filt(), B.make_opts(),
      [B.F2dTensor(FAKE, B.F32, 0, 1, 3, 32, 40, 3840, 1280, 20)], B.EINVAL, "stride_h"),
-    ("u8 needs int32 filter", _img(B.U8), _filt(), B.make_opts(), [_img(B.I32)], B.EINVAL, "int32"),
+    ("u8 needs int32 or float filter", _img(B.U8), _filt(dtype=B.BF16), B.make_opts(), [_img(B.I32)],
+     B.EINVAL, "int32 or float"),
     ("u8 output must be int32", _img(B.U8), _filt(dtype=B.I32), B.make_opts(), [_img(B.F32)],
      B.EINVAL, "dtype"),
     ("sumsq needs depthwise m=2", _img(B.U8), _filt(dtype=B.I32),
@@ -115,7 +136,7 @@ SEP_CASES = [
     ("null factor", _img(), None, 3, B.make_opts(), _img(), B.EINVAL, "NULL"),
     ("even K", _img(), FAKE, 4, B.make_opts(), _img(), B.EINVAL, "odd"),
     ("K beyond the built range", _img(), FAKE, 17, B.make_opts(), _img(), B.EUNSUPPORTED, "1..15"),
-    ("u8 image", _img(B.U8), FAKE, 3, B.make_opts(), _img(B.I32), B.EINVAL, "int32"),
+    ("u8 image", _img(B.U8), FAKE, 3, B.make_opts(), _img(B.I32), B.EUNSUPPORTED, "f32 images only"),
     ("depthwise mode", _img(), FAKE, 3, B.make_opts("depthwise"), _img(), B.EUNSUPPORTED, "SHARED"),
     ("wrong output shape", _img(), FAKE, 3, B.make_opts(), _img(w=39), B.EINVAL, "shape"),
     ("band outside image", _img(h=32), FAKE, 3, B.make_opts(rows=(10, 40)), _img(h=30), B.EINVAL,
@@ -198,6 +219,32 @@ def test_backward_noalloc_validation_on_the_host(lib):
     big32 = B.F2dTensor(FAKE, B.BF16, 0, 32, c, h, w, c * h * w, h * w, w)
     assert lib.filter2d_backward_workspace(ctypes.byref(big32), ctypes.byref(bf),
                                            ctypes.byref(bopts)) <= NOALLOC_SCRATCH_BYTES
+
+
+UP_CASES = [
+    # (description, image, filter, scale, opts, out, expected status, message fragment)
+    ("scale 0", _img(B.U8), _filt(dtype=B.F32), 0, B.make_opts(), _img(B.U8), B.EINVAL, "scale"),
+    ("f32 image", _img(), _filt(), 2, B.make_opts(), _img(h=64, w=80), B.EUNSUPPORTED, "u8 images only"),
+    ("depthwise", _img(B.U8), _filt(f_out=3, dtype=B.I32), 2, B.make_opts("depthwise"),
+     _img(B.U8, h=64, w=80), B.EUNSUPPORTED, "SHARED"),
+    ("band", _img(B.U8), _filt(dtype=B.F32), 2, B.make_opts(rows=(0, 16)), _img(B.U8, h=32, w=80),
+     B.EUNSUPPORTED, "whole images"),
+    ("wrong out shape", _img(B.U8), _filt(dtype=B.F32), 2, B.make_opts(), _img(B.U8, h=64, w=79),
+     B.EINVAL, "H*scale"),
+    ("wrong out dtype", _img(B.U8), _filt(dtype=B.F32), 2, B.make_opts(), _img(B.I32, h=64, w=80),
+     B.EINVAL, "dtype"),
+    ("k 9", _img(B.U8), _filt(k=9, dtype=B.F32), 2, B.make_opts(), _img(B.U8, h=64, w=80),
+     B.EUNSUPPORTED, "k <= 7"),
+]
+
+
+@pytest.mark.parametrize("case", UP_CASES, ids=[c[0] for c in UP_CASES])
+def test_upsample_forward_rejects_on_the_host(lib, case):
+    _, image, filt, scale, opts, out, status, frag = case
+    st = lib.filter2d_upsample_forward(ctypes.byref(image), ctypes.byref(filt), scale, ctypes.byref(opts),
+                                       ctypes.byref(out), None)
+    assert st == status
+    assert frag.lower() in B.last_error().lower()
 
 
 def test_batched_plan_validation_on_the_host(lib):
