@@ -302,20 +302,26 @@ def oracle_one_core(rows, k):
 
 # -------------------------------------------------------------------- suite --
 
-def suite(torch, B, wl, reps):
+def suite(torch, B, wl, reps, only=None):
     t = Timer(torch)
     res = {}
 
-    # device ceilings: a plain fill and a device copy (torch kernels)
-    a = torch.empty(298598400, dtype=torch.int32, device="cuda")  # 1.19 GB, the Sobel outputs
-    ms_fill = t.per_call_ms(lambda: a.fill_(7), reps)
-    b = torch.empty(1 << 28, dtype=torch.float32, device="cuda")
-    c = torch.empty_like(b)
-    ms_copy = t.per_call_ms(lambda: c.copy_(b), reps)
-    res["device_ceilings"] = {"fill_1.19GB_GBs": round(a.numel() * 4 / (ms_fill * 1e-3) / 1e9, 1),
-                              "copy_1GiB_GBs": round(2 * b.numel() * 4 / (ms_copy * 1e-3) / 1e9, 1)}
-    del a, b, c
-    torch.cuda.empty_cache()
+    import re as _re
+
+    def want(name):
+        return only is None or _re.search(only, name) is not None
+
+    if want('device_ceilings'):
+        # device ceilings: a plain fill and a device copy (torch kernels)
+        a = torch.empty(298598400, dtype=torch.int32, device="cuda")  # 1.19 GB, the Sobel outputs
+        ms_fill = t.per_call_ms(lambda: a.fill_(7), reps)
+        b = torch.empty(1 << 28, dtype=torch.float32, device="cuda")
+        c = torch.empty_like(b)
+        ms_copy = t.per_call_ms(lambda: c.copy_(b), reps)
+        res["device_ceilings"] = {"fill_1.19GB_GBs": round(a.numel() * 4 / (ms_fill * 1e-3) / 1e9, 1),
+                                  "copy_1GiB_GBs": round(2 * b.numel() * 4 / (ms_copy * 1e-3) / 1e9, 1)}
+        del a, b, c
+        torch.cuda.empty_cache()
 
     # plain FP32 forward, 1024^2, 5x5 Gaussian: launch-latency bound, so timed
     # by replaying a graph of 100 launches
@@ -344,170 +350,219 @@ def suite(torch, B, wl, reps):
                             "note": "8.4 MB working set: latency-bound, HBM % not meaningful"}
     del g
 
-    # 8K Sobel (u8 -> int32 gx, gy, gx^2 + gy^2): HBM bound, 92% writes
-    x, f = wl.sobel()
-    xd, fd = torch.from_numpy(x).cuda(), torch.from_numpy(f).cuda()
-    outs = [torch.empty(x.shape, dtype=torch.int32, device="cuda") for _ in range(3)]
-    variant = B.autotune_forward(xd, fd, mode="depthwise", epilogue=B.EPI_SUMSQ_PAIRS, reps=5)
-    ms = t.per_call_ms(lambda: B.forward(xd, fd, mode="depthwise", epilogue=B.EPI_SUMSQ_PAIRS, outs=outs), reps)
-    pix = x.size
-    alg = pix * 1 + 3 * pix * 4
-    res["sobel_u8_8k"] = {"shape": "1x3x4320x7680 u8, Sobel-x/y + gx^2+gy^2 (int32)", "ms": round(ms, 4),
-                          "variant": variant, "mpix_taps_s": round(pix * 18 / (ms * 1e-3) / 1e6, 1),
-                          "vs_plain_fwd": round(pix * 18 / (ms * 1e-3) / 1e6 / plain, 3),
-                          "roofline": roof("hbm", alg / (ms * 1e-3) / 1e9, HBM_PEAK_GBS, "GB/s",
-                                           measured_traffic("sobel_u8_8k", ["paper_2504_01266_amd/csrc/stencil_u8.hip"]),
-                                           algorithmic_bytes_per_launch=alg)}
-    del xd, outs
-    torch.cuda.empty_cache()
+    if want('sobel_u8_8k'):
+        # 8K Sobel (u8 -> int32 gx, gy, gx^2 + gy^2): HBM bound, 92% writes
+        x, f = wl.sobel()
+        xd, fd = torch.from_numpy(x).cuda(), torch.from_numpy(f).cuda()
+        outs = [torch.empty(x.shape, dtype=torch.int32, device="cuda") for _ in range(3)]
+        variant = B.autotune_forward(xd, fd, mode="depthwise", epilogue=B.EPI_SUMSQ_PAIRS, reps=5)
+        ms = t.per_call_ms(lambda: B.forward(xd, fd, mode="depthwise", epilogue=B.EPI_SUMSQ_PAIRS, outs=outs), reps)
+        pix = x.size
+        alg = pix * 1 + 3 * pix * 4
+        res["sobel_u8_8k"] = {"shape": "1x3x4320x7680 u8, Sobel-x/y + gx^2+gy^2 (int32)", "ms": round(ms, 4),
+                              "variant": variant, "mpix_taps_s": round(pix * 18 / (ms * 1e-3) / 1e6, 1),
+                              "vs_plain_fwd": round(pix * 18 / (ms * 1e-3) / 1e6 / plain, 3),
+                              "roofline": roof("hbm", alg / (ms * 1e-3) / 1e9, HBM_PEAK_GBS, "GB/s",
+                                               measured_traffic("sobel_u8_8k", ["paper_2504_01266_amd/csrc/stencil_u8.hip"]),
+                                               algorithmic_bytes_per_launch=alg)}
+        del xd, outs
+        torch.cuda.empty_cache()
 
-    # FP32 forward 16x3x2048^2, 9x9 (VALU bound without packed FP32)
-    xs = np.stack([wl.diff_image(i) for i in range(16)])
-    f9 = wl.diff_filter()
-    xd, fd = torch.from_numpy(xs).cuda(), torch.from_numpy(f9).cuda()
-    out = torch.empty_like(xd)
-    ms = t.per_call_ms(lambda: B.forward(xd, fd, outs=[out]), reps)
-    pt = xs.size * 81
-    res["diff_f32_fwd"] = {"shape": "16x3x2048x2048 f32, 9x9", "ms": round(ms, 4),
-                           "mpix_taps_s": round(pt / (ms * 1e-3) / 1e6, 1),
-                           "vs_plain_fwd": round(pt / (ms * 1e-3) / 1e6 / plain, 3),
-                           "roofline": roof("alu", 2.0 * pt / (ms * 1e-3) / 1e12, FP32_VALU_PEAK_TFLOPS, "TFLOP/s"),
-                           "hbm_gbs": round(xs.size * 8 / (ms * 1e-3) / 1e9, 1)}
-    gs = np.stack([wl.diff_grad(i) for i in range(16)])
-    gd = torch.from_numpy(gs).cuda()
-    del gs
-    ws = torch.empty(B.backward_workspace(xd, fd), dtype=torch.uint8, device="cuda")
-
-    def fwd_bwd():
-        B.forward(xd, fd, outs=[out])
-        B.backward(xd, fd, gd, workspace=ws)
-
-    ms_fb = t.per_call_ms(fwd_bwd, reps)
-    ms_b = t.per_call_ms(lambda: B.backward(xd, fd, gd, workspace=ws), reps)
-    pt3 = 3 * pt
-    res["diff_f32_fwd_bwd"] = {"shape": "16x3x2048x2048 f32, 9x9, fwd + grad_input + grad_filter",
-                               "ms": round(ms_fb, 4), "bwd_ms": round(ms_b, 4),
-                               "mpix_taps_s": round(pt3 / (ms_fb * 1e-3) / 1e6, 1),
-                               "vs_plain_fwd": round(pt3 / (ms_fb * 1e-3) / 1e6 / plain, 3),
-                               "roofline": roof("alu", 2.0 * pt3 / (ms_fb * 1e-3) / 1e12, FP32_VALU_PEAK_TFLOPS,
-                                                "TFLOP/s")}
-    # separable fast path on the same images: the 9x9 normalised Gaussian
-    # (sigma 2) as g g^T, 2K = 18 multiply-adds per output, against the direct
-    # K x K path with the same filter
-    g9 = wl.gaussian_factor(9, 2.0)
-    gk = torch.from_numpy(g9).cuda()
-    fgg = torch.from_numpy(np.outer(g9, g9).astype(np.float32)).cuda()
-    ms_sep = t.per_call_ms(lambda: B.forward_separable(xd, gk, gk, out=out), reps)
-    ms_dir = t.per_call_ms(lambda: B.forward(xd, fgg, outs=[out]), reps)
-    ps = xs.size * 18
-    res["separable_f32_fwd"] = {"shape": "16x3x2048x2048 f32, 9x9 Gaussian as g g^T (18 taps per output)",
-                                "ms": round(ms_sep, 4), "direct_ms": round(ms_dir, 4),
-                                "speedup_vs_direct": round(ms_dir / ms_sep, 3),
-                                "mpix_taps_s": round(ps / (ms_sep * 1e-3) / 1e6, 1),
-                                "vs_plain_fwd": round(ps / (ms_sep * 1e-3) / 1e6 / plain, 3),
-                                "roofline": roof("hbm", xs.size * 8 / (ms_sep * 1e-3) / 1e9, HBM_PEAK_GBS, "GB/s")}
-    del xd, out, gd, ws, gk, fgg
-    torch.cuda.empty_cache()
-
-    # zero borders (the paper's sharpen skips out-of-image neighbours): the
-    # 3x3 Laplacian on a 3-channel 4K frame, against clamp-to-edge on the same
-    xz = torch.from_numpy(wl.sharpen_frame()).cuda()
-    lap = torch.from_numpy(wl.LAPLACIAN_8).cuda()
-    oz = torch.empty_like(xz)
-    ms_z = t.per_call_ms(lambda: B.forward(xz, lap, outs=[oz], border="zero"), reps)
-    ms_c = t.per_call_ms(lambda: B.forward(xz, lap, outs=[oz]), reps)
-    pz = xz.numel()
-    res["zero_border_f32_fwd"] = {"shape": "1x3x2160x3840 f32 (0..255), 3x3 Laplacian sharpen, zero borders",
-                                  "ms": round(ms_z, 4), "clamp_ms": round(ms_c, 4),
-                                  "mpix_taps_s": round(pz * 9 / (ms_z * 1e-3) / 1e6, 1),
-                                  "vs_plain_fwd": round(pz * 9 / (ms_z * 1e-3) / 1e6 / plain, 3),
-                                  "roofline": roof("hbm", pz * 8 / (ms_z * 1e-3) / 1e9, HBM_PEAK_GBS, "GB/s")}
-    del xz, oz, lap
-    torch.cuda.empty_cache()
-
-    # ragged batch: 64 images, H, W uniform in [256, 4096], 3 channels, 7x7
-    # each, one launch; against the 64 single-image calls on the same images
-    sizes = wl.ragged_sizes()
-    xd, yd, fdl = [], [], []
-    for i, (h, w) in enumerate(sizes):
-        xi, fi = wl.ragged_item(i, int(h), int(w))
-        xd.append(torch.from_numpy(xi).cuda())
-        yd.append(torch.empty_like(xd[-1]))
-        fdl.append(torch.from_numpy(fi).cuda())
-    batch = B.RaggedBatch(xd, yd, fdl)
-    variant = batch.autotune(reps=3)
-    ms = t.per_call_ms(batch.run, reps)
-
-    def singles():
-        for x_, f_, y_ in zip(xd, fdl, yd):
-            B.forward(x_, f_, outs=[y_])
-
-    ms_single = t.per_call_ms(singles, max(2, reps // 2))
-    px = sum(x.numel() for x in xd)
-    pt = px * 49
-    res["ragged_batch_f32"] = {"shape": f"64 images, {px} px-channels, 7x7, one launch",
-                               "ms": round(ms, 4), "single_calls_ms": round(ms_single, 4),
-                               "tiles": batch.total_tiles, "variant": variant,
+    if want('diff_f32'):
+        # FP32 forward 16x3x2048^2, 9x9 (VALU bound without packed FP32)
+        xs = np.stack([wl.diff_image(i) for i in range(16)])
+        f9 = wl.diff_filter()
+        xd, fd = torch.from_numpy(xs).cuda(), torch.from_numpy(f9).cuda()
+        out = torch.empty_like(xd)
+        ms = t.per_call_ms(lambda: B.forward(xd, fd, outs=[out]), reps)
+        pt = xs.size * 81
+        res["diff_f32_fwd"] = {"shape": "16x3x2048x2048 f32, 9x9", "ms": round(ms, 4),
                                "mpix_taps_s": round(pt / (ms * 1e-3) / 1e6, 1),
                                "vs_plain_fwd": round(pt / (ms * 1e-3) / 1e6 / plain, 3),
                                "roofline": roof("alu", 2.0 * pt / (ms * 1e-3) / 1e12, FP32_VALU_PEAK_TFLOPS, "TFLOP/s"),
-                               "hbm_frac": round(px * 8 / (ms * 1e-3) / 1e9 / HBM_PEAK_GBS, 4)}
-    del xd, yd, fdl, batch
-    torch.cuda.empty_cache()
+                               "hbm_gbs": round(xs.size * 8 / (ms * 1e-3) / 1e9, 1)}
+        gs = np.stack([wl.diff_grad(i) for i in range(16)])
+        gd = torch.from_numpy(gs).cuda()
+        del gs
+        ws = torch.empty(B.backward_workspace(xd, fd), dtype=torch.uint8, device="cuda")
 
-    # BF16 filter bank, each call on its own, K = 3 and 5
-    for k in (3, 5):
-        bt = bank_tensors(torch, wl, k)
-        xb, gb, wb = bt["x"], bt["g"], bt["w"]
-        bb = bank_bytes(k)
-        y32 = torch.empty((BANK_N, BANK_CO, BANK_HW, BANK_HW), device="cuda")
-        y16 = torch.empty((BANK_N, BANK_CO, BANK_HW, BANK_HW), dtype=torch.bfloat16, device="cuda")
-        gi = torch.empty((BANK_N, BANK_CI, BANK_HW, BANK_HW), device="cuda")
-        ws = torch.empty(B.backward_workspace(xb, wb, mode="bank"), dtype=torch.uint8, device="cuda")
-        entry = {"shape": f"32x16x1024x1024 bf16 -> 64 ch, {k}x{k}"}
-        for name, fn, key in (
-                ("fwd_f32out", lambda: B.forward(xb, wb, mode="bank", outs=[y32]), "fwd_f32out"),
-                ("fwd_bf16out", lambda: B.forward(xb, wb, mode="bank", outs=[y16]), "fwd_bf16out"),
-                ("dgrad", lambda: B.backward(xb, wb, gb, mode="bank", need_filter=False, workspace=ws,
-                                             grad_input=gi), "dgrad"),
-                ("wgrad", lambda: B.backward(xb, wb, gb, mode="bank", need_input=False, workspace=ws), "wgrad")):
+        def fwd_bwd():
+            B.forward(xd, fd, outs=[out])
+            B.backward(xd, fd, gd, workspace=ws)
+
+        ms_fb = t.per_call_ms(fwd_bwd, reps)
+        ms_b = t.per_call_ms(lambda: B.backward(xd, fd, gd, workspace=ws), reps)
+        pt3 = 3 * pt
+        res["diff_f32_fwd_bwd"] = {"shape": "16x3x2048x2048 f32, 9x9, fwd + grad_input + grad_filter",
+                                   "ms": round(ms_fb, 4), "bwd_ms": round(ms_b, 4),
+                                   "mpix_taps_s": round(pt3 / (ms_fb * 1e-3) / 1e6, 1),
+                                   "vs_plain_fwd": round(pt3 / (ms_fb * 1e-3) / 1e6 / plain, 3),
+                                   "roofline": roof("alu", 2.0 * pt3 / (ms_fb * 1e-3) / 1e12, FP32_VALU_PEAK_TFLOPS,
+                                                    "TFLOP/s")}
+        # separable fast path on the same images: the 9x9 normalised Gaussian
+        # (sigma 2) as g g^T, 2K = 18 multiply-adds per output, against the direct
+        # K x K path with the same filter
+        g9 = wl.gaussian_factor(9, 2.0)
+        gk = torch.from_numpy(g9).cuda()
+        fgg = torch.from_numpy(np.outer(g9, g9).astype(np.float32)).cuda()
+        ms_sep = t.per_call_ms(lambda: B.forward_separable(xd, gk, gk, out=out), reps)
+        ms_dir = t.per_call_ms(lambda: B.forward(xd, fgg, outs=[out]), reps)
+        ps = xs.size * 18
+        res["separable_f32_fwd"] = {"shape": "16x3x2048x2048 f32, 9x9 Gaussian as g g^T (18 taps per output)",
+                                    "ms": round(ms_sep, 4), "direct_ms": round(ms_dir, 4),
+                                    "speedup_vs_direct": round(ms_dir / ms_sep, 3),
+                                    "mpix_taps_s": round(ps / (ms_sep * 1e-3) / 1e6, 1),
+                                    "vs_plain_fwd": round(ps / (ms_sep * 1e-3) / 1e6 / plain, 3),
+                                    "roofline": roof("hbm", xs.size * 8 / (ms_sep * 1e-3) / 1e9, HBM_PEAK_GBS, "GB/s")}
+        del xd, out, gd, ws, gk, fgg
+        torch.cuda.empty_cache()
+
+    if want('zero_border_f32_fwd'):
+        # zero borders (the paper's sharpen skips out-of-image neighbours): the
+        # 3x3 Laplacian on a 3-channel 4K frame, against clamp-to-edge on the same
+        xz = torch.from_numpy(wl.sharpen_frame()).cuda()
+        lap = torch.from_numpy(wl.LAPLACIAN_8).cuda()
+        oz = torch.empty_like(xz)
+        ms_z = t.per_call_ms(lambda: B.forward(xz, lap, outs=[oz], border="zero"), reps)
+        ms_c = t.per_call_ms(lambda: B.forward(xz, lap, outs=[oz]), reps)
+        pz = xz.numel()
+        res["zero_border_f32_fwd"] = {"shape": "1x3x2160x3840 f32 (0..255), 3x3 Laplacian sharpen, zero borders",
+                                      "ms": round(ms_z, 4), "clamp_ms": round(ms_c, 4),
+                                      "mpix_taps_s": round(pz * 9 / (ms_z * 1e-3) / 1e6, 1),
+                                      "vs_plain_fwd": round(pz * 9 / (ms_z * 1e-3) / 1e6 / plain, 3),
+                                      "roofline": roof("hbm", pz * 8 / (ms_z * 1e-3) / 1e9, HBM_PEAK_GBS, "GB/s")}
+        del xz, oz, lap
+        torch.cuda.empty_cache()
+
+    if want('paper_u8'):
+        # the paper's own image operations on 8-bit RGB (interleaved, as OpenCV
+        # delivers it): the float Laplacian sharpen with skipped out-of-image
+        # neighbours, 8-bit out (Section 4.2.4); the same after nearest
+        # upsampling by 2, 4 and 20 in one pass (Sections 4.2.3, 6.6); the
+        # grayscale weights on an 8K frame (Section 4.2.5)
+        x4k = wl.paper_frame_u8()
+        xd = torch.from_numpy(x4k).cuda()[None].permute(0, 3, 1, 2)
+        lap = torch.from_numpy(wl.LAPLACIAN_8).cuda()
+        px_in = x4k.size
+        for s_up in (1, 2, 4, 20):
+            out = torch.empty((1, x4k.shape[0] * s_up, x4k.shape[1] * s_up, 3), dtype=torch.uint8,
+                              device="cuda").permute(0, 3, 1, 2)
+            if s_up == 1:
+                fn = lambda: B.forward(xd, lap, border="zero", outs=[out])  # noqa: E731
+            else:
+                fn = lambda: B.upsample_forward(xd, lap, s_up, out=out, border="zero")  # noqa: E731
             ms = t.per_call_ms(fn, reps)
-            entry[name] = {"ms": round(ms, 4),
-                           "hbm_frac": round(bb[key] / (ms * 1e-3) / 1e9 / HBM_PEAK_GBS, 4),
-                           "mfma_frac": round(bb["flops"] / (ms * 1e-3) / 1e12 / BF16_MFMA_PEAK_TFLOPS, 4)}
-
-        def fb():
-            B.forward(xb, wb, mode="bank", outs=[y32])
-            B.backward(xb, wb, gb, mode="bank", workspace=ws, grad_input=gi)
-
-        ms_fb = t.per_call_ms(fb, reps)
-        entry["fwd_bwd_ms"] = round(ms_fb, 4)
-        entry["fwd_bwd_mpix_taps_s"] = round(3 * bb["taps"] / (ms_fb * 1e-3) / 1e6, 1)
-        entry["vs_plain_fwd"] = round(3 * bb["taps"] / (ms_fb * 1e-3) / 1e6 / plain, 3)
-        res[f"bank_bf16_k{k}"] = entry
-        del bt, xb, gb, wb, y32, y16, gi, ws
+            px_out = out.numel()
+            res[f"paper_sharpen_u8_x{s_up}"] = {
+                "shape": f"4K RGB u8 interleaved (2160x3840x3) -> x{s_up} nearest upsample -> 3x3 Laplacian, "
+                         f"zero borders, u8 out ({px_out} values)",
+                "ms": round(ms, 4), "mpix_taps_s": round(px_out * 9 / (ms * 1e-3) / 1e6, 1),
+                "vs_plain_fwd": round(px_out * 9 / (ms * 1e-3) / 1e6 / plain, 3),
+                "roofline": roof("hbm", (px_in + px_out) / (ms * 1e-3) / 1e9, HBM_PEAK_GBS, "GB/s",
+                                 algorithmic_bytes_per_launch=px_in + px_out)}
+            del out
+            torch.cuda.empty_cache()
+        del xd
+        x8k = wl.paper_frame_u8(4320, 7680)
+        xd = torch.from_numpy(x8k).cuda()[None].permute(0, 3, 1, 2)
+        gw = torch.from_numpy(wl.GRAY_RGB.astype(np.float32).reshape(1, 3, 1, 1)).cuda()
+        gout = torch.empty((1, 1, 4320, 7680), dtype=torch.uint8, device="cuda")
+        ms = t.per_call_ms(lambda: B.forward(xd, gw, mode="bank", outs=[gout]), reps)
+        alg = x8k.size + gout.numel()
+        res["paper_grayscale_u8_8k"] = {
+            "shape": "8K RGB u8 interleaved (4320x7680x3) -> gray u8 (0.299, 0.587, 0.114)",
+            "ms": round(ms, 4), "mpix_taps_s": round(gout.numel() * 3 / (ms * 1e-3) / 1e6, 1),
+            "vs_plain_fwd": round(gout.numel() * 3 / (ms * 1e-3) / 1e6 / plain, 3),
+            "roofline": roof("hbm", alg / (ms * 1e-3) / 1e9, HBM_PEAK_GBS, "GB/s", algorithmic_bytes_per_launch=alg)}
+        del xd, gout
         torch.cuda.empty_cache()
 
-    # the FP32 comparison path (VALU): the same 32-image bank in FP32
-    for k in (3, 5):
-        bt = bank_tensors(torch, wl, k, fp32=True)
-        x32, g32, w32 = bt["x32"], bt["g32"], bt["w32"]
-        del bt
+    if want('ragged_batch_f32'):
+        # ragged batch: 64 images, H, W uniform in [256, 4096], 3 channels, 7x7
+        # each, one launch; against the 64 single-image calls on the same images
+        sizes = wl.ragged_sizes()
+        xd, yd, fdl = [], [], []
+        for i, (h, w) in enumerate(sizes):
+            xi, fi = wl.ragged_item(i, int(h), int(w))
+            xd.append(torch.from_numpy(xi).cuda())
+            yd.append(torch.empty_like(xd[-1]))
+            fdl.append(torch.from_numpy(fi).cuda())
+        batch = B.RaggedBatch(xd, yd, fdl)
+        variant = batch.autotune(reps=3)
+        ms = t.per_call_ms(batch.run, reps)
+
+        def singles():
+            for x_, f_, y_ in zip(xd, fdl, yd):
+                B.forward(x_, f_, outs=[y_])
+
+        ms_single = t.per_call_ms(singles, max(2, reps // 2))
+        px = sum(x.numel() for x in xd)
+        pt = px * 49
+        res["ragged_batch_f32"] = {"shape": f"64 images, {px} px-channels, 7x7, one launch",
+                                   "ms": round(ms, 4), "single_calls_ms": round(ms_single, 4),
+                                   "tiles": batch.total_tiles, "variant": variant,
+                                   "mpix_taps_s": round(pt / (ms * 1e-3) / 1e6, 1),
+                                   "vs_plain_fwd": round(pt / (ms * 1e-3) / 1e6 / plain, 3),
+                                   "roofline": roof("alu", 2.0 * pt / (ms * 1e-3) / 1e12, FP32_VALU_PEAK_TFLOPS, "TFLOP/s"),
+                                   "hbm_frac": round(px * 8 / (ms * 1e-3) / 1e9 / HBM_PEAK_GBS, 4)}
+        del xd, yd, fdl, batch
         torch.cuda.empty_cache()
-        bb = bank_bytes(k)
-        y = torch.empty((BANK_N, BANK_CO, BANK_HW, BANK_HW), device="cuda")
-        gi = torch.empty_like(x32)
-        ws = torch.empty(B.backward_workspace(x32, w32, mode="bank"), dtype=torch.uint8, device="cuda")
-        ms_f = t.per_call_ms(lambda: B.forward(x32, w32, mode="bank", outs=[y]), 2, warmup=1)
-        ms_b = t.per_call_ms(lambda: B.backward(x32, w32, g32, mode="bank", workspace=ws, grad_input=gi), 2, warmup=1)
-        res[f"bank_f32_k{k}"] = {"shape": f"32x16x1024x1024 f32 -> 64 ch f32, {k}x{k} (VALU path)",
-                                 "fwd_ms": round(ms_f, 3), "bwd_ms": round(ms_b, 3),
-                                 "fwd_mpix_taps_s": round(bb["taps"] / (ms_f * 1e-3) / 1e6, 1),
-                                 "fwd_bwd_mpix_taps_s": round(3 * bb["taps"] / ((ms_f + ms_b) * 1e-3) / 1e6, 1),
-                                 "fwd_valu_frac": round(bb["flops"] / (ms_f * 1e-3) / 1e12 / FP32_VALU_PEAK_TFLOPS, 4),
-                                 "bwd_valu_frac": round(2 * bb["flops"] / (ms_b * 1e-3) / 1e12 / FP32_VALU_PEAK_TFLOPS, 4)}
-        del x32, g32, w32, y, gi, ws
-        torch.cuda.empty_cache()
+
+    if want('bank_bf16'):
+        # BF16 filter bank, each call on its own, K = 3 and 5
+        for k in (3, 5):
+            bt = bank_tensors(torch, wl, k)
+            xb, gb, wb = bt["x"], bt["g"], bt["w"]
+            bb = bank_bytes(k)
+            y32 = torch.empty((BANK_N, BANK_CO, BANK_HW, BANK_HW), device="cuda")
+            y16 = torch.empty((BANK_N, BANK_CO, BANK_HW, BANK_HW), dtype=torch.bfloat16, device="cuda")
+            gi = torch.empty((BANK_N, BANK_CI, BANK_HW, BANK_HW), device="cuda")
+            ws = torch.empty(B.backward_workspace(xb, wb, mode="bank"), dtype=torch.uint8, device="cuda")
+            entry = {"shape": f"32x16x1024x1024 bf16 -> 64 ch, {k}x{k}"}
+            for name, fn, key in (
+                    ("fwd_f32out", lambda: B.forward(xb, wb, mode="bank", outs=[y32]), "fwd_f32out"),
+                    ("fwd_bf16out", lambda: B.forward(xb, wb, mode="bank", outs=[y16]), "fwd_bf16out"),
+                    ("dgrad", lambda: B.backward(xb, wb, gb, mode="bank", need_filter=False, workspace=ws,
+                                                 grad_input=gi), "dgrad"),
+                    ("wgrad", lambda: B.backward(xb, wb, gb, mode="bank", need_input=False, workspace=ws), "wgrad")):
+                ms = t.per_call_ms(fn, reps)
+                entry[name] = {"ms": round(ms, 4),
+                               "hbm_frac": round(bb[key] / (ms * 1e-3) / 1e9 / HBM_PEAK_GBS, 4),
+                               "mfma_frac": round(bb["flops"] / (ms * 1e-3) / 1e12 / BF16_MFMA_PEAK_TFLOPS, 4)}
+
+            def fb():
+                B.forward(xb, wb, mode="bank", outs=[y32])
+                B.backward(xb, wb, gb, mode="bank", workspace=ws, grad_input=gi)
+
+            ms_fb = t.per_call_ms(fb, reps)
+            entry["fwd_bwd_ms"] = round(ms_fb, 4)
+            entry["fwd_bwd_mpix_taps_s"] = round(3 * bb["taps"] / (ms_fb * 1e-3) / 1e6, 1)
+            entry["vs_plain_fwd"] = round(3 * bb["taps"] / (ms_fb * 1e-3) / 1e6 / plain, 3)
+            res[f"bank_bf16_k{k}"] = entry
+            del bt, xb, gb, wb, y32, y16, gi, ws
+            torch.cuda.empty_cache()
+
+    if want('bank_f32'):
+        # the FP32 comparison path (VALU): the same 32-image bank in FP32
+        for k in (3, 5):
+            bt = bank_tensors(torch, wl, k, fp32=True)
+            x32, g32, w32 = bt["x32"], bt["g32"], bt["w32"]
+            del bt
+            torch.cuda.empty_cache()
+            bb = bank_bytes(k)
+            y = torch.empty((BANK_N, BANK_CO, BANK_HW, BANK_HW), device="cuda")
+            gi = torch.empty_like(x32)
+            ws = torch.empty(B.backward_workspace(x32, w32, mode="bank"), dtype=torch.uint8, device="cuda")
+            ms_f = t.per_call_ms(lambda: B.forward(x32, w32, mode="bank", outs=[y]), 2, warmup=1)
+            ms_b = t.per_call_ms(lambda: B.backward(x32, w32, g32, mode="bank", workspace=ws, grad_input=gi), 2, warmup=1)
+            res[f"bank_f32_k{k}"] = {"shape": f"32x16x1024x1024 f32 -> 64 ch f32, {k}x{k} (VALU path)",
+                                     "fwd_ms": round(ms_f, 3), "bwd_ms": round(ms_b, 3),
+                                     "fwd_mpix_taps_s": round(bb["taps"] / (ms_f * 1e-3) / 1e6, 1),
+                                     "fwd_bwd_mpix_taps_s": round(3 * bb["taps"] / ((ms_f + ms_b) * 1e-3) / 1e6, 1),
+                                     "fwd_valu_frac": round(bb["flops"] / (ms_f * 1e-3) / 1e12 / FP32_VALU_PEAK_TFLOPS, 4),
+                                     "bwd_valu_frac": round(2 * bb["flops"] / (ms_b * 1e-3) / 1e12 / FP32_VALU_PEAK_TFLOPS, 4)}
+            del x32, g32, w32, y, gi, ws
+            torch.cuda.empty_cache()
     return res
 
 
@@ -640,6 +695,7 @@ def main():
     ap.add_argument("--k", type=int, default=5, help="bank filter size of the headline (3 or 5)")
     ap.add_argument("--no-suite", action="store_true", help="headline workload only")
     ap.add_argument("--suite-reps", type=int, default=5)
+    ap.add_argument("--suite-only", default=None, help="regex: run only the suite entries it matches")
     ap.add_argument("--cpu-seconds", type=float, default=15.0, help="oracle sample budget")
     ap.add_argument("--no-cpu", action="store_true", help="skip the oracle baseline and parity")
     ap.add_argument("--profile", action="store_true",
@@ -698,7 +754,7 @@ def main():
     sres = None
     if not args.no_suite:
         log("bench: suite")
-        sres = suite(torch, B, wl, args.suite_reps)
+        sres = suite(torch, B, wl, args.suite_reps, args.suite_only)
     k = args.k
     line = {
         "metric": "Mpix*taps/s (BF16 bank fwd+bwd; suite: other workloads vs plain FP32 fwd); "

@@ -192,7 +192,7 @@ f2d_status filter2d_forward_separable(const f2d_tensor* image, const float* a, c
  *
  *   image   [N][C][H][W] U8, planar or interleaved (as filter2d_forward)
  *   filter  [1][1][k][k], odd k <= 7, I32 or F32 taps
- *   scale   >= 1 (1 is filter2d_forward)
+ *   scale   1..4096 (1 is filter2d_forward)
  *   opts    channels SHARED, epilogue NONE, whole images (row_begin = 0 and
  *           row_end = 0 or H); border CLAMP or ZERO
  *   out     [N][C][H*scale][W*scale] in the image's layout: U8 (clamped and

@@ -364,7 +364,7 @@ f2d_status filter2d_upsample_forward(const f2d_tensor* image, const f2d_filter* 
   Problem pr;
   f2d_status s = check_common(image, filter, opts, &pr);
   if (s) return s;
-  if (scale < 1) return fail(F2D_EINVAL, "upsample: scale %d < 1", scale);
+  if (scale < 1 || scale > 4096) return fail(F2D_EINVAL, "upsample: scale %d outside 1..4096", scale);
   if (image->dtype != F2D_U8) return fail(F2D_EUNSUPPORTED, "upsample: u8 images only");
   if (opts->channels != F2D_CH_SHARED) return fail(F2D_EUNSUPPORTED, "upsample: SHARED channel mode only");
   if (opts->epilogue != F2D_EPI_NONE) return fail(F2D_EINVAL, "upsample: no epilogue");

@@ -87,6 +87,7 @@ struct BankParams {
   int32_t fr;
   int32_t d_vec;  // output rows and planes 16-byte (f32) / 8-byte (bf16) aligned
   int32_t s_vec;  // source rows and planes 16-byte aligned and W % 8 == 0 (vector staging)
+  int32_t s_plan32;  // s_vec, and one image of the source spans < 2^31 elements with H, s_sh < 2^24
 };
 
 // FP32 -> BF16, round to nearest even (NaN stays NaN): the gfx950 packed
@@ -609,7 +610,10 @@ __global__ __launch_bounds__(64 * NW) void k_bank_conv(BankParams p) {
     oy0 = static_cast<int64_t>(tile_y) * kTH;
     ox0 = (ADJ ? p.col0 : 0) + static_cast<int64_t>(tile_x) * G::TW;
   };
-  int64_t t = blockIdx.x;
+  // XCD-aware start: the work-groups resident on one XCD take consecutive
+  // tiles, so the halo lines neighbouring tiles share are read once into
+  // that XCD's L2 (the stride below keeps every round contiguous)
+  int64_t t = xcd_remap(blockIdx.x, gridDim.x);
   if (t >= p.n_tiles) return;
   int64_t n, oy0, ox0;
   int og;
@@ -693,6 +697,80 @@ __global__ __launch_bounds__(64 * NW) void k_bank_conv(BankParams p) {
 // oldest rows once no wave reads them any more: for K > kTH packed between
 // the MFMA groups of the last tap rows' steps, after a barrier (two barriers
 // per tile), else after the sweep, between two barriers.
+// The ring kernel's per-tile staging of the NEW rows, planned once per
+// column segment.  Everything about a staging unit that does not change from
+// one tile to the next (its channel and clamped chunk column as a 32-bit
+// element offset into image n, its LDS offset within a ring row, its row and
+// flags) is computed when the segment starts; a tile then only adds its row.
+// Used with vector staging when one source image spans < 2^31 elements.
+template <int NTN>
+struct RingPlan {
+  uint32_t soff[NTN];  // element offset of the unit's chunk in image n, row 0
+  uint32_t loff[NTN];  // LDS element offset within a ring row
+  uint32_t info[NTN];  // row (bits 0-7) | active << 8 | channel kept << 9 | outside (1 left, 2 right) << 10
+};
+
+template <typename G, int CG, int NR, int NTN>
+__device__ __forceinline__ void ring_plan(const BankParams& p, int64_t ox0, int wave, int lane, RingPlan<NTN>& pl) {
+  const int j = lane >> 3;
+#pragma unroll
+  for (int it = 0; it < NTN; ++it) {
+    int ly, cg, chunk;
+    bool act;
+    unit_pos<G, CG, 8, NR>(it, wave, lane, ly, cg, chunk, act);
+    const int c = cg * 8 + j;
+    const bool keep = c < p.CI;
+    const int64_t cc = keep ? c : p.CI - 1;
+    const int64_t gx0 = ox0 - 8 + 8 * chunk;
+    const int64_t gxl = gx0 < 0 ? 0 : (gx0 > p.W - 8 ? p.W - 8 : gx0);
+    const uint32_t outside = gx0 < 0 ? 1u : (gx0 >= p.W ? 2u : 0u);
+    pl.soff[it] = static_cast<uint32_t>(cc * p.s_sc + gxl);
+    pl.loff[it] = static_cast<uint32_t>((chunk * 8 + j) * G::PS + cg * 8);
+    pl.info[it] = static_cast<uint32_t>(ly) | (act ? 1u << 8 : 0u) | (keep ? 1u << 9 : 0u) | (outside << 10);
+  }
+}
+
+// Loads of the planned units for source rows gy_base + row (clamped).
+template <typename TS, int NTN>
+__device__ __forceinline__ void ring_load(const BankParams& p, const TS* __restrict__ sp_n, int64_t gy_base,
+                                          const RingPlan<NTN>& pl, Raw<TS, NTN>& st) {
+  const int32_t hl = static_cast<int32_t>(p.H) - 1;
+  const uint32_t sh = static_cast<uint32_t>(p.s_sh);
+#pragma unroll
+  for (int it = 0; it < NTN; ++it) {
+    int32_t gy = static_cast<int32_t>(gy_base) + static_cast<int32_t>(pl.info[it] & 0xffu);
+    gy = gy < 0 ? 0 : (gy > hl ? hl : gy);
+    load_vec(sp_n + (pl.soff[it] + __umul24(static_cast<uint32_t>(gy), sh)), st.v[it]);
+  }
+}
+
+// Edge fix, padding, transpose and ring write of planned unit `it` (tile row
+// LH - NR + row goes to ring row (slot0 + LH - NR + row) mod NSLOT).
+template <typename G, bool ADJ, typename TS, int NR, int NTN>
+__device__ __forceinline__ void ring_store_unit(const BankParams& p, int64_t gy_base, int lane, const RingPlan<NTN>& pl,
+                                                const Raw<TS, NTN>& st, uint16_t* __restrict__ ring, int it, int slot0) {
+  const int j = lane >> 3;
+  const uint32_t info = pl.info[it];
+  const int row = static_cast<int>(info & 0xffu);
+  bool keep = (info >> 9) & 1u;
+  if constexpr (ADJ) {
+    const int64_t gy = gy_base + row;
+    keep = keep && gy >= 0 && gy < p.H;
+  }
+  u32x4 d = st.pairs(it);
+  const uint32_t outside = (info >> 10) & 3u;
+  if (outside) {  // chunks outside the row: edge value (clamp) or zero (adjoint)
+    const uint32_t e = outside == 1u ? (d[0] & 0xffffu) : (d[3] >> 16);
+    const uint32_t b = ADJ ? 0u : (e | (e << 16));
+    d = u32x4{b, b, b, b};
+  }
+  if (!keep) d = u32x4{0u, 0u, 0u, 0u};
+  d = transpose8(d, j);
+  int lrow = slot0 + (G::LH - NR) + row;
+  lrow -= lrow >= G::NSLOT ? G::NSLOT : 0;
+  if ((info >> 8) & 1u) *reinterpret_cast<u32x4*>(ring + lrow * (G::LW * G::PS) + pl.loff[it]) = d;
+}
+
 template <int K, int OT, int PT, int CG, bool ADJ, typename TS, bool OUT_BF16>
 __global__ __launch_bounds__(512) void k_bank_conv_ring(BankParams p) {
   using G = ConvGeom<K, OT, PT, CG, 8>;
@@ -726,7 +804,9 @@ __global__ __launch_bounds__(512) void k_bank_conv_ring(BankParams p) {
   const uint32_t spc = static_cast<uint32_t>(p.seg_per_col), tx = static_cast<uint32_t>(p.tiles_x);
   const uint32_t ngr = static_cast<uint32_t>(p.o_groups);
   int og_loaded = -1;
-  for (int64_t sg = blockIdx.x; sg < p.n_segs; sg += gridDim.x) {
+  // XCD-aware start (see k_bank_conv): horizontally adjacent column
+  // segments run on one XCD at the same time and share their halo lines in L2
+  for (int64_t sg = xcd_remap(blockIdx.x, gridDim.x); sg < p.n_segs; sg += gridDim.x) {
     const uint32_t col = static_cast<uint32_t>(sg) / spc, sy = static_cast<uint32_t>(sg) - col * spc;
     const uint32_t tile_x = col % tx, ng = col / tx;
     const int og = static_cast<int>(ng % ngr);
@@ -752,14 +832,26 @@ __global__ __launch_bounds__(512) void k_bank_conv_ring(BankParams p) {
     }
     int slot = 0;
     __syncthreads();
-    Raw<TS, staging_nt<G, 8, NEW>()> st;
+    constexpr int NTN = staging_nt<G, 8, NEW>();
+    Raw<TS, NTN> st;
+    const bool planned = p.s_plan32 != 0;  // uniform
+    RingPlan<NTN> pl;
+    if (planned) ring_plan<G, CG, NEW, NTN>(p, ox0, wave, lane, pl);
+    const TS* sp_n = static_cast<const TS*>(p.src) + n * p.s_sn;
     for (int ty = ty0; ty < ty1; ++ty) {
       const int64_t oy0 = static_cast<int64_t>(ty) * kTH;
       const bool more = ty + 1 < ty1;  // uniform
+      // source row of planned row 0 of the next tile's NEW rows
+      const int64_t gy_next = p.row0 + oy0 + kTH - G::R + (G::LH - NEW);
       swave = wave;
       slane = lane;
-      asm volatile("" : "+s"(swave), "+v"(slane));
-      if (more) stage_load<G, K, CG, ADJ, TS, 8, NEW>(p, n, oy0 + kTH, ox0, swave, slane, st, G::LH - NEW);
+      if (!planned) asm volatile("" : "+s"(swave), "+v"(slane));
+      if (more) {
+        if (planned)
+          ring_load<TS, NTN>(p, sp_n, gy_next, pl, st);
+        else
+          stage_load<G, K, CG, ADJ, TS, 8, NEW>(p, n, oy0 + kTH, ox0, swave, slane, st, G::LH - NEW);
+      }
       __builtin_amdgcn_sched_barrier(0);
       // ring row of this wave's tap row u (uniform), then the lane's pixel
       const uint16_t* ring_lane = ring + lane_off;
@@ -777,7 +869,6 @@ __global__ __launch_bounds__(512) void k_bank_conv_ring(BankParams p) {
           r -= r >= G::NSLOT ? G::NSLOT : 0;
           return ring_lane + r * ROWE + ((t % K) * G::PS + ((4 * st8) % CG) * 8);
         };
-        constexpr int NTN = staging_nt<G, 8, NEW>();
         constexpr int S0 = G::STEPS > NTN ? G::STEPS - NTN : 0;
         mfma_sweep<G, K, CG, OTP, HP>(w_lane + P * OTP * 16 * G::WSTR, xsrc, q, acc,
                                       [&](auto step) __attribute__((always_inline)) {
@@ -788,9 +879,13 @@ __global__ __launch_bounds__(512) void k_bank_conv_ring(BankParams p) {
               constexpr int SS = OVL ? S0 : (SB > S0 ? SB : S0);
               constexpr int u0 = s8 - SS, u1 = s8 == G::STEPS - 1 ? NTN : s8 - SS + 1;
 #pragma unroll
-              for (int u = u0 < 0 ? 0 : u0; u < u1; ++u)
-                stage_store_unit<G, K, CG, ADJ, TS, 8, NEW, true>(p, oy0 + kTH, ox0, swave, slane, st, ring, u,
-                                                                 G::LH - NEW, nslot);
+              for (int u = u0 < 0 ? 0 : u0; u < u1; ++u) {
+                if (planned)
+                  ring_store_unit<G, ADJ, TS, NEW, NTN>(p, gy_next, lane, pl, st, ring, u, nslot);
+                else
+                  stage_store_unit<G, K, CG, ADJ, TS, 8, NEW, true>(p, oy0 + kTH, ox0, swave, slane, st, ring, u,
+                                                                   G::LH - NEW, nslot);
+              }
             }
           }
         });
@@ -800,8 +895,13 @@ __global__ __launch_bounds__(512) void k_bank_conv_ring(BankParams p) {
       if (more) {
         __syncthreads();  // (OVL, LATE: the new rows are packed; all reads of the oldest rows done)
         if constexpr (!OVL && !LATE) {  // the oldest kTH ring rows become the next tile's new rows
-          stage_store<G, K, CG, ADJ, TS, 8, NEW, true>(p, oy0 + kTH, ox0, swave, slane, st, ring, G::LH - NEW,
-                                                      nslot);
+          if (planned) {
+#pragma unroll
+            for (int u = 0; u < NTN; ++u) ring_store_unit<G, ADJ, TS, NEW, NTN>(p, gy_next, lane, pl, st, ring, u, nslot);
+          } else {
+            stage_store<G, K, CG, ADJ, TS, 8, NEW, true>(p, oy0 + kTH, ox0, swave, slane, st, ring, G::LH - NEW,
+                                                        nslot);
+          }
           __syncthreads();
         }
         slot = nslot;
@@ -918,7 +1018,10 @@ __global__ __launch_bounds__(64 * (kWsMfma + kWsMem)) void k_bank_conv_ws(BankPa
   // Both roles walk the same tiles and pass the same barriers (one per tile,
   // plus one when the output group changes); each role has its own loop, so
   // that its registers are not held across the other role's code.
-  int64_t t = blockIdx.x;
+  // XCD-aware start: the work-groups resident on one XCD take consecutive
+  // tiles, so the halo lines neighbouring tiles share are read once into
+  // that XCD's L2 (the stride below keeps every round contiguous)
+  int64_t t = xcd_remap(blockIdx.x, gridDim.x);
   if (t >= p.n_tiles) return;
   int64_t n, oy0, ox0;
   int og;
@@ -1191,7 +1294,9 @@ __global__ __launch_bounds__(kThreads) __attribute__((amdgpu_waves_per_eu(2))) v
   for (int e = 0; e < K * K; ++e) acc[e] = f32x4{0.f, 0.f, 0.f, 0.f};
 
   const int64_t per_image = static_cast<int64_t>(p.tiles_x) * p.tiles_y;
-  for (int64_t t = blockIdx.x; t < p.n_tiles; t += p.units) {
+  // XCD-aware start: the units on one XCD take consecutive tiles (whole tile
+  // rows of one image), whose X halo rows and columns then come from L2
+  for (int64_t t = xcd_remap(blockIdx.x, p.units); t < p.n_tiles; t += p.units) {
     const int64_t n = t / per_image, r = t - n * per_image;
     const int64_t y0 = (r / p.tiles_x) * kWgTH, x0 = (r % p.tiles_x) * kWgTW;
     const uint16_t* xp = p.x + n * p.x_sn;
@@ -1416,6 +1521,13 @@ bool conv_shape(int64_t ci, int64_t co, int k, int* ot, int* cg) {
 }
 
 // persistent wgrad grid: units work-groups over n_tiles tiles
+// One image of a staged source (c channels) spans < 2^31 elements, with H
+// and the row stride below 2^24 (the ring kernel's 32-bit staging offsets).
+bool plan32_fits(const f2d_tensor& t, int64_t c) {
+  const int64_t extent = (c - 1) * t.stride_c + (t.h - 1) * t.stride_h + t.w;
+  return extent < (int64_t{1} << 31) && t.h < (int64_t{1} << 24) && t.stride_h < (int64_t{1} << 24);
+}
+
 size_t wgrad_bytes(const Problem& pr, int32_t* units, int64_t* n_tiles, int32_t* tx, int32_t* ty) {
   const f2d_tensor& im = pr.image;
   *tx = static_cast<int32_t>((im.w + kWgTW - 1) / kWgTW);
@@ -1441,6 +1553,7 @@ f2d_status bank_forward_bf16(const Problem& pr, const f2d_tensor* outs, hipStrea
   p.s_sc = im.stride_c;
   p.s_sh = im.stride_h;
   p.s_vec = row_aligned(im, 16) && im.w % 8 == 0 ? 1 : 0;
+  p.s_plan32 = p.s_vec && plan32_fits(im, im.c) ? 1 : 0;
   p.dst = out.data;
   p.d_sn = out.stride_n;
   p.d_sc = out.stride_c;
@@ -1498,6 +1611,7 @@ f2d_status bank_backward_bf16(const Problem& pr, const f2d_tensor& gout, const f
     p.s_sc = gout.stride_c;
     p.s_sh = gout.stride_h;
     p.s_vec = row_aligned(gout, 16) && im.w % 8 == 0 ? 1 : 0;
+    p.s_plan32 = p.s_vec && plan32_fits(gout, pr.c_out) ? 1 : 0;
     p.dst = grad_input->data;
     p.d_sn = grad_input->stride_n;
     p.d_sc = grad_input->stride_c;

@@ -31,6 +31,7 @@
 // [0, 255] and rounded to nearest, ties to even.
 #include <hip/hip_runtime.h>
 
+#include <algorithm>
 #include <cstring>
 
 #include "f2d_host.hpp"
@@ -46,7 +47,6 @@ constexpr int kOutU8 = 2;
 constexpr int kGThreads = 256;
 constexpr int kGElems = 8;                   // output elements per lane and row
 constexpr int kGTW = kGThreads * kGElems;    // 2048 elements per tile row
-constexpr int kGTH = 32;                     // output rows per tile
 constexpr int kGPitchWords = (kGTW + 32) / 4;  // staged row: 2048 + 2rC (<= 2072) bytes + read slack
 
 struct GatherParams {
@@ -59,12 +59,23 @@ struct GatherParams {
   int64_t Hout, Wout;  // H*s, W*s
   int64_t row0, out_rows;  // output rows [row0, row0 + out_rows) of the (upsampled) buffer
   int32_t s;         // nearest-upsample factor
+  uint32_t s_magic;  // division by s: q = (t + ((x - t) >> 1)) >> s_shift, t = mulhi(x, s_magic)
+  int32_t s_shift;   // (s >= 2; Granlund and Montgomery's method for invariant divisors)
   int32_t zero;      // zero borders (else clamp-to-edge)
   int32_t planes_c;  // planes per image on the grid: C (planar) or 1 (interleaved)
+  int32_t th;        // output rows per tile
+  int32_t lds_rows;  // staged source rows per tile (at most); one more zero row follows
   int32_t tiles_x, tiles_y;
   int64_t n_blocks;
   int32_t vec;  // output rows aligned for the lanes' vector stores
 };
+
+// x / s for 0 <= x < 2^32 with the launch's invariant-divisor constants
+__device__ __forceinline__ uint32_t div_s(uint32_t x, const GatherParams& p) {
+  if (p.s == 1) return x;
+  const uint32_t t = __umulhi(x, p.s_magic);
+  return (t + ((x - t) >> 1)) >> p.s_shift;
+}
 
 template <int K, int P, bool TF, int OUT>
 __global__ __launch_bounds__(kGThreads) void k_u8_gather(GatherParams p) {
@@ -73,11 +84,10 @@ __global__ __launch_bounds__(kGThreads) void k_u8_gather(GatherParams p) {
   constexpr int WIN = kGTW + 2 * RP;          // staged elements per row
   constexpr int WORDS = (WIN + 3) / 4;
   constexpr int NW = (kGElems + 2 * RP + 3) / 4;  // words of a lane's window
-  constexpr int MAXROWS = kGTH + 2 * R;       // distinct source rows of a tile (s = 1)
-  constexpr int ZROW = MAXROWS;              // an all-zero row for zero borders
   static_assert(WORDS <= kGPitchWords && 2 * (kGThreads - 1) + NW <= kGPitchWords, "staged row too short");
-  __shared__ uint32_t lds[(MAXROWS + 1) * kGPitchWords];
+  extern __shared__ uint32_t lds[];
   using Acc = typename std::conditional<TF, float, uint32_t>::type;
+  const int zrow = p.lds_rows;                // an all-zero row for zero borders
 
   const int tid = threadIdx.x;
   const int64_t b = xcd_remap(blockIdx.x, p.n_blocks);
@@ -90,21 +100,20 @@ __global__ __launch_bounds__(kGThreads) void k_u8_gather(GatherParams p) {
   const int64_t c = plane - n * p.planes_c;
   const uint8_t* sp = p.src + n * p.s_sn + c * p.s_sc;
   const int64_t e0 = tx * kGTW;               // first output element of the tile
-  const int64_t y0 = ty * kGTH;               // first output row (band-relative)
+  const int64_t y0 = ty * p.th;               // first output row (band-relative)
   const int64_t L = p.Wout * P;               // elements per output row
-  const int64_t s = p.s;
-  const int64_t nrow_out = min(static_cast<int64_t>(kGTH), p.out_rows - y0);
+  const int64_t nrow_out = min(static_cast<int64_t>(p.th), p.out_rows - y0);
 
   // source rows the tile reads: the upsampled rows t = row0 + y + u - R,
-  // clamped to [0, Hout) (zero-border rows outside are the zero row)
+  // clamped to [0, Hout) (zero-border rows outside are the zero row);
+  // indices fit in 32 bits (at most 2^30 rows and elements per row)
   auto clamp_out_row = [&](int64_t t) { return t < 0 ? int64_t{0} : (t >= p.Hout ? p.Hout - 1 : t); };
-  const int64_t rlo = clamp_out_row(p.row0 + y0 - R) / s;
-  const int64_t rhi = clamp_out_row(p.row0 + y0 + nrow_out - 1 + R) / s;
-  const int nsrc = static_cast<int>(rhi - rlo + 1);
+  const int32_t rlo = static_cast<int32_t>(div_s(static_cast<uint32_t>(clamp_out_row(p.row0 + y0 - R)), p));
+  const int32_t rhi =
+      static_cast<int32_t>(div_s(static_cast<uint32_t>(clamp_out_row(p.row0 + y0 + nrow_out - 1 + R)), p));
+  const int nsrc = rhi - rlo + 1;  // <= lds_rows (host sizing)
 
   // ---- stage: row-expanded source bytes of every source row of the tile
-  // (element and pixel indices fit in 32 bits: rows of at most 2^30 elements)
-  const uint32_t s32 = static_cast<uint32_t>(p.s);
   const int32_t wout = static_cast<int32_t>(p.Wout);
   for (int q = tid; q < WORDS; q += kGThreads) {
     int32_t off[4];
@@ -119,17 +128,17 @@ __global__ __launch_bounds__(kGThreads) void k_u8_gather(GatherParams p) {
         xc = xu < 0 ? 0 : wout - 1;
         inside = true;
       }
-      off[jj] = inside ? static_cast<int32_t>(static_cast<uint32_t>(xc) / s32) * P + ch : -1;
+      off[jj] = inside ? static_cast<int32_t>(div_s(static_cast<uint32_t>(xc), p)) * P + ch : -1;
     }
     for (int ri = 0; ri < nsrc; ++ri) {
-      const uint8_t* rp = sp + (rlo + ri) * p.s_sh;
+      const uint8_t* rp = sp + static_cast<int64_t>(rlo + ri) * p.s_sh;
       uint32_t w = 0;
 #pragma unroll
       for (int jj = 0; jj < 4; ++jj)
         if (off[jj] >= 0) w |= static_cast<uint32_t>(rp[off[jj]]) << (8 * jj);
       lds[ri * kGPitchWords + q] = w;
     }
-    lds[ZROW * kGPitchWords + q] = 0u;
+    lds[zrow * kGPitchWords + q] = 0u;
   }
   __syncthreads();
 
@@ -138,7 +147,18 @@ __global__ __launch_bounds__(kGThreads) void k_u8_gather(GatherParams p) {
 #pragma unroll
   for (int i = 0; i < K * K; ++i) tap[i] = static_cast<const Acc*>(p.taps)[i];
 
-  // ---- walk the rows
+  // ---- walk the rows.  Tap row u of output row y reads upsampled row
+  // t = row0 + y + u - R, i.e. source row q_u with t = q_u s + m_u; (q_u, m_u)
+  // advance with y, so no division is needed inside the loop.
+  int32_t qd[K], md[K];
+#pragma unroll
+  for (int u = 0; u < K; ++u) {
+    const int64_t t = p.row0 + y0 + u - R;  // >= -R
+    const uint32_t tp = static_cast<uint32_t>(t + 4 * p.s);  // shifted to stay non-negative
+    qd[u] = static_cast<int32_t>(div_s(tp, p)) - 4;
+    md[u] = static_cast<int32_t>(t - static_cast<int64_t>(qd[u]) * p.s);
+  }
+  const int32_t hlast = static_cast<int32_t>(p.H - 1);
   int32_t prev[K];
 #pragma unroll
   for (int u = 0; u < K; ++u) prev[u] = -1;
@@ -152,13 +172,19 @@ __global__ __launch_bounds__(kGThreads) void k_u8_gather(GatherParams p) {
     for (int u = 0; u < K; ++u) {
       const int64_t t = p.row0 + y + u - R;
       int32_t r;
-      if ((t < 0 || t >= p.Hout) && p.zero)
-        r = ZROW;
+      if (t < 0)
+        r = p.zero ? zrow : -rlo;
+      else if (t >= p.Hout)
+        r = p.zero ? zrow : hlast - rlo;
       else
-        r = static_cast<int32_t>(static_cast<uint32_t>(clamp_out_row(t)) / s32 - static_cast<uint32_t>(rlo));
+        r = qd[u] - rlo;
       ridx[u] = r;
       same = same && r == prev[u];
       prev[u] = r;
+      if (++md[u] == p.s) {
+        md[u] = 0;
+        ++qd[u];
+      }
     }
     if (!same) {
       Acc acc[kGElems];
@@ -365,17 +391,23 @@ bool rows_aligned(const f2d_tensor& t, size_t bytes) {
          (t.n <= 1 || (t.stride_n * es) % bytes == 0);
 }
 
+template <int K, int P, bool TF, int OUT>
+hipError_t launch_gather_one(const GatherParams& g, hipStream_t s) {
+  const void* kern = reinterpret_cast<const void*>(k_u8_gather<K, P, TF, OUT>);
+  const size_t lds = static_cast<size_t>(g.lds_rows + 1) * kGPitchWords * 4;
+  if (lds > 64 * 1024) {
+    hipError_t e = hipFuncSetAttribute(kern, hipFuncAttributeMaxDynamicSharedMemorySize, static_cast<int>(lds));
+    if (e != hipSuccess) return e;
+  }
+  hipLaunchKernelGGL((k_u8_gather<K, P, TF, OUT>), dim3(static_cast<uint32_t>(g.n_blocks)), dim3(kGThreads), lds, s,
+                     g);
+  return hipGetLastError();
+}
+
 template <int K, int P>
 hipError_t launch_gather_kp(const GatherParams& g, bool tf, int out, hipStream_t s) {
-  const dim3 grid(static_cast<uint32_t>(g.n_blocks)), block(kGThreads);
-  if (tf) {
-    if (out == kOutU8) hipLaunchKernelGGL((k_u8_gather<K, P, true, kOutU8>), grid, block, 0, s, g);
-    else hipLaunchKernelGGL((k_u8_gather<K, P, true, kOutF32>), grid, block, 0, s, g);
-  } else {
-    if (out == kOutU8) hipLaunchKernelGGL((k_u8_gather<K, P, false, kOutU8>), grid, block, 0, s, g);
-    else hipLaunchKernelGGL((k_u8_gather<K, P, false, kOutI32>), grid, block, 0, s, g);
-  }
-  return hipGetLastError();
+  if (tf) return out == kOutU8 ? launch_gather_one<K, P, true, kOutU8>(g, s) : launch_gather_one<K, P, true, kOutF32>(g, s);
+  return out == kOutU8 ? launch_gather_one<K, P, false, kOutU8>(g, s) : launch_gather_one<K, P, false, kOutI32>(g, s);
 }
 
 template <int K>
@@ -426,8 +458,21 @@ f2d_status gather_forward(const Problem& pr, const f2d_tensor& out, int32_t scal
   const int64_t L = g.Wout * P;
   if (L > (int64_t{1} << 30) || g.Hout > (int64_t{1} << 30))
     return fail(F2D_EUNSUPPORTED, "u8 filter: output rows of at most 2^30 elements and 2^30 rows");
+  // Tile height: 16 rows without upsampling; with it, about 8 source rows
+  // per tile (rows inside an upsampled block repeat, so the work per tile is
+  // set by its source rows), at most 512 rows.  LDS holds the tile's source
+  // rows: at most (th + 2r - 1) / s + 2 of them.
+  const int R = (pr.k - 1) / 2;
+  g.th = scale == 1 ? 16 : static_cast<int32_t>(std::min<int64_t>(512, 8 * static_cast<int64_t>(scale)));
+  g.lds_rows = std::min(g.th + 2 * R, (g.th + 2 * R - 1) / scale + 2);
+  if (scale > 1) {
+    int l = 0;
+    while ((int64_t{1} << l) < scale) ++l;
+    g.s_shift = l - 1;
+    g.s_magic = static_cast<uint32_t>((((uint64_t{1} << 32) * ((uint64_t{1} << l) - scale)) / scale) + 1);
+  }
   g.tiles_x = static_cast<int32_t>((L + kGTW - 1) / kGTW);
-  g.tiles_y = static_cast<int32_t>((g.out_rows + kGTH - 1) / kGTH);
+  g.tiles_y = static_cast<int32_t>((g.out_rows + g.th - 1) / g.th);
   g.n_blocks = im.n * g.planes_c * static_cast<int64_t>(g.tiles_x) * g.tiles_y;
   if (g.n_blocks > kMaxBlocks) return fail(F2D_EUNSUPPORTED, "u8 filter: too many tiles for one launch");
   g.vec = rows_aligned(out, ok_out == kOutU8 ? 8 : 16) ? 1 : 0;
