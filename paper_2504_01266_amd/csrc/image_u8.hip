@@ -113,14 +113,20 @@ __global__ __launch_bounds__(kGThreads) void k_u8_gather(GatherParams p) {
       static_cast<int32_t>(div_s(static_cast<uint32_t>(clamp_out_row(p.row0 + y0 + nrow_out - 1 + R)), p));
   const int nsrc = rhi - rlo + 1;  // <= lds_rows (host sizing)
 
-  // ---- stage: row-expanded source bytes of every source row of the tile
+  // ---- stage: row-expanded source bytes of every source row of the tile.
+  // A thread owns window words tid + 256 k (k < NQ); their source offsets
+  // are computed once, then the loads of two source rows for all its words
+  // are issued before any of them is written, so a tile pays about nsrc / 2
+  // load latencies.  Offsets < 0 are zero-border elements.
+  constexpr int NQ = (WORDS + kGThreads - 1) / kGThreads;
   const int32_t wout = static_cast<int32_t>(p.Wout);
-  for (int q = tid; q < WORDS; q += kGThreads) {
-    int32_t off[4];
+  int32_t off[NQ][4];
+#pragma unroll
+  for (int k = 0; k < NQ; ++k)
 #pragma unroll
     for (int jj = 0; jj < 4; ++jj) {
-      const int32_t e = static_cast<int32_t>(e0) - RP + 4 * q + jj;  // >= -RP
-      const int32_t xu = (e + P * 4) / P - 4;                      // floor(e / P)
+      const int32_t e = static_cast<int32_t>(e0) - RP + 4 * (tid + kGThreads * k) + jj;  // >= -RP
+      const int32_t xu = (e + P * 4) / P - 4;                                          // floor(e / P)
       const int32_t ch = e - xu * P;
       int32_t xc = xu;
       bool inside = xu >= 0 && xu < wout;
@@ -128,18 +134,38 @@ __global__ __launch_bounds__(kGThreads) void k_u8_gather(GatherParams p) {
         xc = xu < 0 ? 0 : wout - 1;
         inside = true;
       }
-      off[jj] = inside ? static_cast<int32_t>(div_s(static_cast<uint32_t>(xc), p)) * P + ch : -1;
+      off[k][jj] = inside ? static_cast<int32_t>(div_s(static_cast<uint32_t>(xc), p)) * P + ch : -1;
     }
-    for (int ri = 0; ri < nsrc; ++ri) {
-      const uint8_t* rp = sp + static_cast<int64_t>(rlo + ri) * p.s_sh;
-      uint32_t w = 0;
+  for (int ri = 0; ri < nsrc; ri += 2) {
+    const bool two = ri + 1 < nsrc;  // uniform
+    const uint8_t* rp0 = sp + static_cast<int64_t>(rlo + ri) * p.s_sh;
+    const uint8_t* rp1 = two ? rp0 + p.s_sh : rp0;
+    uint32_t b[2][NQ][4];
 #pragma unroll
-      for (int jj = 0; jj < 4; ++jj)
-        if (off[jj] >= 0) w |= static_cast<uint32_t>(rp[off[jj]]) << (8 * jj);
-      lds[ri * kGPitchWords + q] = w;
+    for (int k = 0; k < NQ; ++k)
+#pragma unroll
+      for (int jj = 0; jj < 4; ++jj) {
+        const int32_t o = off[k][jj] < 0 ? 0 : off[k][jj];
+        b[0][k][jj] = rp0[o];
+        b[1][k][jj] = rp1[o];
+      }
+#pragma unroll
+    for (int k = 0; k < NQ; ++k) {
+      const int q = tid + kGThreads * k;
+      if (q >= WORDS) continue;
+#pragma unroll
+      for (int h = 0; h < 2; ++h) {
+        uint32_t w = 0;
+#pragma unroll
+        for (int jj = 0; jj < 4; ++jj)
+          if (off[k][jj] >= 0) w |= b[h][k][jj] << (8 * jj);
+        if (h == 0 || two) lds[(ri + h) * kGPitchWords + q] = w;
+      }
     }
-    lds[zrow * kGPitchWords + q] = 0u;
   }
+#pragma unroll
+  for (int k = 0; k < NQ; ++k)
+    if (tid + kGThreads * k < WORDS) lds[zrow * kGPitchWords + tid + kGThreads * k] = 0u;
   __syncthreads();
 
   // ---- taps (uniform)
