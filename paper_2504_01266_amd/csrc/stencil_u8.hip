@@ -297,6 +297,9 @@ hipError_t by_variant(const StencilParams& p, int variant, hipStream_t stream) {
     case 2: return go<K, M, SUMSQ, 8, false>(p, stream);
     case 3: return go<K, M, SUMSQ, 32, false>(p, stream);
     case 4: return go<K, M, SUMSQ, 16, true>(p, stream);
+    case 5: return go<K, M, SUMSQ, 8, true>(p, stream);
+    case 6: return go<K, M, SUMSQ, 4, false>(p, stream);
+    case 7: return go<K, M, SUMSQ, 4, true>(p, stream);
     default: return go<K, M, SUMSQ, 16, false>(p, stream);
   }
 }
@@ -314,14 +317,15 @@ hipError_t by_m(const StencilParams& p, int m, bool sumsq, int variant, hipStrea
 
 TileShape u8_tile(int variant) {
   switch (variant) {
-    case 2: return {kWaves * 8, kTW};
+    case 2: case 5: return {kWaves * 8, kTW};
     case 3: return {kWaves * 32, kTW};
+    case 6: case 7: return {kWaves * 4, kTW};
     case -1: return {16, 16};  // generic kernel
     default: return {kWaves * 16, kTW};
   }
 }
 
-int u8_variant_count() { return 4; }
+int u8_variant_count() { return 7; }
 
 // m is 1 or 2 for the templated kernels (K <= 9); variant < 0 selects
 // the generic kernel, which handles m <= 2 for any odd K <= 31.

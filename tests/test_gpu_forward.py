@@ -137,7 +137,7 @@ def test_sobel_bit_exact(gpu_lib, shape):
     assert torch.equal(m.cpu(), torch.from_numpy(mm.astype(np.int32)))
 
 
-@pytest.mark.parametrize("variant", [1, 2, 3, 4])
+@pytest.mark.parametrize("variant", [1, 2, 3, 4, 5, 6, 7])
 def test_u8_variants_and_large_taps_wrap(gpu_lib, variant):
     """Taps too large for the 24-bit multiplier take the 32-bit path; the
     int32 results wrap modulo 2^32 exactly like the int64 oracle cast to int32."""
