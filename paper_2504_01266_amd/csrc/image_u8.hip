@@ -45,9 +45,15 @@ constexpr int kOutF32 = 1;
 constexpr int kOutU8 = 2;
 
 constexpr int kGThreads = 256;
-constexpr int kGElems = 8;                   // output elements per lane and row
-constexpr int kGTW = kGThreads * kGElems;    // 2048 elements per tile row
-constexpr int kGPitchWords = (kGTW + 32) / 4;  // staged row: 2048 + 2rC (<= 2072) bytes + read slack
+// A lane produces E = 8 or 16 consecutive output elements per row (16 for
+// 8-bit outputs of an image upsampled by 8 or more: one 16-byte store per
+// lane and row);
+// a tile row is 256 E elements, a staged row 256 E + 2rC bytes plus slack.
+template <int E>
+struct GTile {
+  static constexpr int TW = kGThreads * E;
+  static constexpr int PITCH_WORDS = (TW + 32) / 4;
+};
 
 struct GatherParams {
   const uint8_t* src;  // element (n, c, 0, 0): planar planes, or interleaved rows (stride_c 1)
@@ -77,14 +83,17 @@ __device__ __forceinline__ uint32_t div_s(uint32_t x, const GatherParams& p) {
   return (t + ((x - t) >> 1)) >> p.s_shift;
 }
 
-template <int K, int P, bool TF, int OUT>
+template <int K, int P, bool TF, int OUT, int E>
 __global__ __launch_bounds__(kGThreads) void k_u8_gather(GatherParams p) {
+  constexpr int kGElems = E;
+  constexpr int kGTW = GTile<E>::TW;
+  constexpr int kGPitchWords = GTile<E>::PITCH_WORDS;
   constexpr int R = (K - 1) / 2;
   constexpr int RP = R * P;
   constexpr int WIN = kGTW + 2 * RP;          // staged elements per row
   constexpr int WORDS = (WIN + 3) / 4;
   constexpr int NW = (kGElems + 2 * RP + 3) / 4;  // words of a lane's window
-  static_assert(WORDS <= kGPitchWords && 2 * (kGThreads - 1) + NW <= kGPitchWords, "staged row too short");
+  static_assert(WORDS <= kGPitchWords && (E / 4) * (kGThreads - 1) + NW <= kGPitchWords, "staged row too short");
   extern __shared__ uint32_t lds[];
   using Acc = typename std::conditional<TF, float, uint32_t>::type;
   const int zrow = p.lds_rows;                // an all-zero row for zero borders
@@ -188,7 +197,7 @@ __global__ __launch_bounds__(kGThreads) void k_u8_gather(GatherParams p) {
   int32_t prev[K];
 #pragma unroll
   for (int u = 0; u < K; ++u) prev[u] = -1;
-  uint32_t outw[OUT == kOutU8 ? 2 : kGElems];
+  uint32_t outw[OUT == kOutU8 ? E / 4 : kGElems];
   const int64_t ebase = e0 + kGElems * tid;
   for (int64_t i = 0; i < nrow_out; ++i) {
     const int64_t y = y0 + i;
@@ -218,7 +227,7 @@ __global__ __launch_bounds__(kGThreads) void k_u8_gather(GatherParams p) {
       for (int j = 0; j < kGElems; ++j) acc[j] = Acc(0);
 #pragma unroll
       for (int u = 0; u < K; ++u) {
-        const uint32_t* row = lds + ridx[u] * kGPitchWords + 2 * tid;
+        const uint32_t* row = lds + ridx[u] * kGPitchWords + (E / 4) * tid;
         uint32_t w[NW];
 #pragma unroll
         for (int k2 = 0; k2 < NW; ++k2) w[k2] = row[k2];
@@ -246,8 +255,9 @@ __global__ __launch_bounds__(kGThreads) void k_u8_gather(GatherParams p) {
             q8[j] = static_cast<uint32_t>(v < 0 ? 0 : (v > 255 ? 255 : v));
           }
         }
-        outw[0] = q8[0] | (q8[1] << 8) | (q8[2] << 16) | (q8[3] << 24);
-        outw[1] = q8[4] | (q8[5] << 8) | (q8[6] << 16) | (q8[7] << 24);
+#pragma unroll
+        for (int w4 = 0; w4 < E / 4; ++w4)
+          outw[w4] = q8[4 * w4] | (q8[4 * w4 + 1] << 8) | (q8[4 * w4 + 2] << 16) | (q8[4 * w4 + 3] << 24);
       } else {
 #pragma unroll
         for (int j = 0; j < kGElems; ++j) outw[j] = __builtin_bit_cast(uint32_t, acc[j]);
@@ -258,7 +268,10 @@ __global__ __launch_bounds__(kGThreads) void k_u8_gather(GatherParams p) {
       if constexpr (OUT == kOutU8) {
         uint8_t* dp = static_cast<uint8_t*>(p.dst) + n * p.d_sn + c * p.d_sc + y * p.d_sh + ebase;
         if (p.vec && ebase + kGElems <= L) {
-          *reinterpret_cast<uint2*>(dp) = make_uint2(outw[0], outw[1]);
+          if constexpr (E == 16)
+            *reinterpret_cast<uint4*>(dp) = make_uint4(outw[0], outw[1], outw[2], outw[3]);
+          else
+            *reinterpret_cast<uint2*>(dp) = make_uint2(outw[0], outw[1]);
         } else {
 #pragma unroll
           for (int j = 0; j < kGElems; ++j)
@@ -267,8 +280,10 @@ __global__ __launch_bounds__(kGThreads) void k_u8_gather(GatherParams p) {
       } else {
         uint32_t* dp = static_cast<uint32_t*>(p.dst) + n * p.d_sn + c * p.d_sc + y * p.d_sh + ebase;
         if (p.vec && ebase + kGElems <= L) {
-          reinterpret_cast<uint4*>(dp)[0] = make_uint4(outw[0], outw[1], outw[2], outw[3]);
-          reinterpret_cast<uint4*>(dp)[1] = make_uint4(outw[4], outw[5], outw[6], outw[7]);
+#pragma unroll
+          for (int w4 = 0; w4 < E / 4; ++w4)
+            reinterpret_cast<uint4*>(dp)[w4] =
+                make_uint4(outw[4 * w4], outw[4 * w4 + 1], outw[4 * w4 + 2], outw[4 * w4 + 3]);
         } else {
 #pragma unroll
           for (int j = 0; j < kGElems; ++j)
@@ -417,31 +432,36 @@ bool rows_aligned(const f2d_tensor& t, size_t bytes) {
          (t.n <= 1 || (t.stride_n * es) % bytes == 0);
 }
 
-template <int K, int P, bool TF, int OUT>
+template <int K, int P, bool TF, int OUT, int E>
 hipError_t launch_gather_one(const GatherParams& g, hipStream_t s) {
-  const void* kern = reinterpret_cast<const void*>(k_u8_gather<K, P, TF, OUT>);
-  const size_t lds = static_cast<size_t>(g.lds_rows + 1) * kGPitchWords * 4;
+  const void* kern = reinterpret_cast<const void*>(k_u8_gather<K, P, TF, OUT, E>);
+  const size_t lds = static_cast<size_t>(g.lds_rows + 1) * GTile<E>::PITCH_WORDS * 4;
   if (lds > 64 * 1024) {
     hipError_t e = hipFuncSetAttribute(kern, hipFuncAttributeMaxDynamicSharedMemorySize, static_cast<int>(lds));
     if (e != hipSuccess) return e;
   }
-  hipLaunchKernelGGL((k_u8_gather<K, P, TF, OUT>), dim3(static_cast<uint32_t>(g.n_blocks)), dim3(kGThreads), lds, s,
-                     g);
+  hipLaunchKernelGGL((k_u8_gather<K, P, TF, OUT, E>), dim3(static_cast<uint32_t>(g.n_blocks)), dim3(kGThreads), lds,
+                     s, g);
   return hipGetLastError();
 }
 
+// 16 elements per lane for 8-bit outputs of images upsampled by 8 or more, else 8
 template <int K, int P>
-hipError_t launch_gather_kp(const GatherParams& g, bool tf, int out, hipStream_t s) {
-  if (tf) return out == kOutU8 ? launch_gather_one<K, P, true, kOutU8>(g, s) : launch_gather_one<K, P, true, kOutF32>(g, s);
-  return out == kOutU8 ? launch_gather_one<K, P, false, kOutU8>(g, s) : launch_gather_one<K, P, false, kOutI32>(g, s);
+hipError_t launch_gather_kp(const GatherParams& g, bool tf, int out, int e, hipStream_t s) {
+  if (out == kOutU8) {
+    if (e == 16)
+      return tf ? launch_gather_one<K, P, true, kOutU8, 16>(g, s) : launch_gather_one<K, P, false, kOutU8, 16>(g, s);
+    return tf ? launch_gather_one<K, P, true, kOutU8, 8>(g, s) : launch_gather_one<K, P, false, kOutU8, 8>(g, s);
+  }
+  return tf ? launch_gather_one<K, P, true, kOutF32, 8>(g, s) : launch_gather_one<K, P, false, kOutI32, 8>(g, s);
 }
 
 template <int K>
-hipError_t launch_gather_k(const GatherParams& g, int P, bool tf, int out, hipStream_t s) {
+hipError_t launch_gather_k(const GatherParams& g, int P, bool tf, int out, int e, hipStream_t s) {
   switch (P) {
-    case 1: return launch_gather_kp<K, 1>(g, tf, out, s);
-    case 3: return launch_gather_kp<K, 3>(g, tf, out, s);
-    default: return launch_gather_kp<K, 4>(g, tf, out, s);
+    case 1: return launch_gather_kp<K, 1>(g, tf, out, e, s);
+    case 3: return launch_gather_kp<K, 3>(g, tf, out, e, s);
+    default: return launch_gather_kp<K, 4>(g, tf, out, e, s);
   }
 }
 
@@ -497,20 +517,22 @@ f2d_status gather_forward(const Problem& pr, const f2d_tensor& out, int32_t scal
     g.s_shift = l - 1;
     g.s_magic = static_cast<uint32_t>((((uint64_t{1} << 32) * ((uint64_t{1} << l) - scale)) / scale) + 1);
   }
-  g.tiles_x = static_cast<int32_t>((L + kGTW - 1) / kGTW);
+  const int elems = ok_out == kOutU8 && scale >= 8 ? 16 : 8;  // 16: measured faster from x8 on
+  const int64_t tw = static_cast<int64_t>(kGThreads) * elems;
+  g.tiles_x = static_cast<int32_t>((L + tw - 1) / tw);
   g.tiles_y = static_cast<int32_t>((g.out_rows + g.th - 1) / g.th);
   g.n_blocks = im.n * g.planes_c * static_cast<int64_t>(g.tiles_x) * g.tiles_y;
   if (g.n_blocks > kMaxBlocks) return fail(F2D_EUNSUPPORTED, "u8 filter: too many tiles for one launch");
-  g.vec = rows_aligned(out, ok_out == kOutU8 ? 8 : 16) ? 1 : 0;
+  g.vec = rows_aligned(out, ok_out == kOutU8 ? static_cast<size_t>(elems) : 16) ? 1 : 0;
   if (g.n_blocks == 0) return ok();
-  hipError_t e;
+  hipError_t err;
   switch (pr.k) {
-    case 1: e = launch_gather_k<1>(g, P, tf, ok_out, s); break;
-    case 3: e = launch_gather_k<3>(g, P, tf, ok_out, s); break;
-    case 5: e = launch_gather_k<5>(g, P, tf, ok_out, s); break;
-    default: e = launch_gather_k<7>(g, P, tf, ok_out, s); break;
+    case 1: err = launch_gather_k<1>(g, P, tf, ok_out, elems, s); break;
+    case 3: err = launch_gather_k<3>(g, P, tf, ok_out, elems, s); break;
+    case 5: err = launch_gather_k<5>(g, P, tf, ok_out, elems, s); break;
+    default: err = launch_gather_k<7>(g, P, tf, ok_out, elems, s); break;
   }
-  return hip_status(e, "u8 filter launch");
+  return hip_status(err, "u8 filter launch");
 }
 
 template <int CIN>

@@ -203,8 +203,8 @@ def test_backward_noalloc_validation_on_the_host(lib):
     st = lib.filter2d_backward_noalloc(ctypes.byref(image), ctypes.byref(filt), g, 1,
                                        ctypes.byref(B.make_opts(border="zero")), None, None, None)
     assert st == B.EUNSUPPORTED
-    # a 128-image 5x5 BF16 bank: its workspace is larger than the static scratch
-    n, c, h, w = 128, 16, 1024, 1024
+    # a 256-image 5x5 BF16 bank: its workspace is larger than the static scratch
+    n, c, h, w = 256, 16, 1024, 1024
     big = B.F2dTensor(FAKE, B.BF16, 0, n, c, h, w, c * h * w, h * w, w)
     bf = B.F2dFilter(FAKE, B.BF16, 64, 16, 5)
     bopts = B.make_opts("bank")

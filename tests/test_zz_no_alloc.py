@@ -58,13 +58,13 @@ def test_noalloc_bf16_bank_two_calls(gpu_lib):
 
 
 def test_noalloc_rejects_oversize_without_touching_outputs(gpu_lib):
-    # a 128-image 5x5 bank needs more than the static scratch: F2D_EWORKSPACE,
+    # a 256-image 5x5 bank needs more than the static scratch: F2D_EWORKSPACE,
     # nothing enqueued (checked on tensors small enough to allocate: the
     # status comes from the size check alone, before any device access)
     row_x = torch.zeros((1, 1, 1, 1024), dtype=torch.bfloat16, device="cuda")
     row_g = torch.zeros((1, 1, 1, 1024), dtype=torch.bfloat16, device="cuda")
-    x = row_x.as_strided((128, 16, 1024, 1024), (0, 0, 0, 1))  # broadcast inputs: read-only views
-    g = row_g.as_strided((128, 64, 1024, 1024), (0, 0, 0, 1))
+    x = row_x.as_strided((256, 16, 1024, 1024), (0, 0, 0, 1))  # broadcast inputs: read-only views
+    g = row_g.as_strided((256, 64, 1024, 1024), (0, 0, 0, 1))
     f = torch.zeros((64, 16, 5, 5), dtype=torch.bfloat16, device="cuda")
     gf = torch.full((64, 16, 5, 5), 7.0, device="cuda")
     with pytest.raises(gpu_lib.F2dError) as e:
