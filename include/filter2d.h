@@ -288,8 +288,11 @@ int64_t filter2d_batched_plan(const f2d_batch_item* items, int32_t n_items, int3
                               int32_t k, int32_t* variant, int64_t* tile_prefix);
 
 /*
- * filter2d_batched -- one launch over every tile of every item, one
- * work-group per tile (each finds its item in the prefix table).
+ * filter2d_batched -- one launch over every tile of every item.  Variants
+ * 1..4: one work-group per tile, each finding its item in the prefix table;
+ * variants 5..8 (the same four tilings): one work-group per run of 4
+ * consecutive tiles, staged in 16-byte chunks.  Items must have h and w
+ * below 2^31 (the plan returns F2D_EUNSUPPORTED otherwise).
  * items_dev and tile_prefix_dev (n_items + 2 words) are device copies of the
  * plan's inputs and outputs.  The call reads nothing from them on the host,
  * so it is safe to capture into a hipGraph and replay while the tables stay

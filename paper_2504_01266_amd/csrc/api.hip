@@ -60,7 +60,7 @@ int variant_count(int path) {
   switch (path) {
     case kPathF32: return f32_variant_count();
     case kPathU8: return u8_variant_count();
-    case kPathBatched: return f32_variant_count();
+    case kPathBatched: return batched_variant_count();
     default: return 0;
   }
 }

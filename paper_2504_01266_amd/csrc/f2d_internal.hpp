@@ -76,6 +76,7 @@ struct TileShape {
 TileShape f32_tile(int variant);
 TileShape u8_tile(int variant);
 int f32_variant_count();
+int batched_variant_count();  // ragged batch: 1..4 one tile per work-group, 5..8 pipelined
 int u8_variant_count();
 
 // XCD-aware work-group ordering: the hardware hands work-groups to the 8 XCDs

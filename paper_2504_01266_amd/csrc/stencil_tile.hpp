@@ -87,8 +87,11 @@ __device__ __forceinline__ float* dst_plane(const StencilParams& p, int t, int64
 // addresses are scalar and each load is scalar base + 32-bit lane offset.
 // This shortens single-output kernels; kernels that stage many source planes
 // per tile keep the per-lane form, which measured faster there.
-template <int K, int PX, int PY, bool ADJ, bool UNI = true>
-__device__ __forceinline__ void stage_tile(float* __restrict__ lds, const float* __restrict__ sp,
+//
+// SP is the source pointer type: a plain pointer, or one qualified with the
+// global address space where the compiler cannot infer it.
+template <int K, int PX, int PY, bool ADJ, bool UNI = true, typename SP = const float*>
+__device__ __forceinline__ void stage_tile(float* __restrict__ lds, SP __restrict__ sp,
                                            int64_t sh, int64_t H, int64_t W, int64_t row_base,
                                            int64_t col_base) {
   using G = Geom<K, PX, PY>;
@@ -124,7 +127,7 @@ __device__ __forceinline__ void stage_tile(float* __restrict__ lds, const float*
       const int ly = wave + kWaves * i;
       const int64_t gy = row_base - G::R + (ly < G::LH ? ly : G::LH - 1);
       rval[i] = gy >= 0 && gy < H;
-      const float* rp = sp + (rval[i] ? gy : 0) * sh;
+      const SP rp = sp + (rval[i] ? gy : 0) * sh;
 #pragma unroll
       for (int j = 0; j < CPL; ++j) buf[i][j] = rp[coff[j]];
     }
@@ -144,7 +147,7 @@ __device__ __forceinline__ void stage_tile(float* __restrict__ lds, const float*
       const int ly = wave + kWaves * i;
       int64_t gy = row_base - G::R + (ly < G::LH ? ly : G::LH - 1);
       gy = gy < 0 ? 0 : (gy >= H ? H - 1 : gy);
-      const float* rp = sp + gy * sh;
+      const SP rp = sp + gy * sh;
 #pragma unroll
       for (int j = 0; j < CPL; ++j) buf[i][j] = rp[coff[j]];
     }
@@ -195,14 +198,20 @@ __device__ __forceinline__ void accumulate(const float* __restrict__ lds,
   }
 }
 
-template <int PX>
-__device__ __forceinline__ void store_row(float* __restrict__ dp, int64_t x0, int64_t W, bool vec,
+typedef float f32x4_t __attribute__((ext_vector_type(4)));
+__device__ __forceinline__ void store4(float* p, f32x4_t v) { *reinterpret_cast<f32x4_t*>(p) = v; }
+__device__ __forceinline__ void store4(__attribute__((address_space(1))) float* p, f32x4_t v) {
+  *reinterpret_cast<__attribute__((address_space(1))) f32x4_t*>(p) = v;
+}
+
+// DP: plain or global-address-space output pointer (see stage_tile).
+template <int PX, typename DP = float*>
+__device__ __forceinline__ void store_row(DP __restrict__ dp, int64_t x0, int64_t W, bool vec,
                                           const float (&v)[PX]) {
   if (vec && x0 + PX <= W) {
 #pragma unroll
     for (int q = 0; q < PX / 4; ++q)
-      reinterpret_cast<float4*>(dp + x0)[q] = make_float4(v[4 * q], v[4 * q + 1], v[4 * q + 2],
-                                                          v[4 * q + 3]);
+      store4(dp + x0 + 4 * q, f32x4_t{v[4 * q], v[4 * q + 1], v[4 * q + 2], v[4 * q + 3]});
   } else {
 #pragma unroll
     for (int px = 0; px < PX; ++px)

@@ -260,6 +260,15 @@ def test_batched_plan_validation_on_the_host(lib):
     total = lib.filter2d_batched_plan(items, 2, B.F32, 3, ctypes.byref(var), prefix)
     assert total > 0 and var.value >= 1
     assert prefix[0] == 0 and prefix[2] == total and prefix[1] == total // 2
+    # extents of 2^31 and more are rejected (the kernels clamp in 32 bits)
+    for h, w in ((1 << 31, 12), (10, 1 << 31)):
+        huge = B.F2dBatchItem(FAKE, FAKE, FAKE, 1, h, w, h * w, w, h * w, w)
+        items3 = (B.F2dBatchItem * 1)(huge)
+        assert lib.filter2d_batched_plan(items3, 1, B.F32, 3, ctypes.byref(var), prefix) == -B.EUNSUPPORTED
+        assert "2^31" in B.last_error()
+    # variants past the last are rejected
+    var = ctypes.c_int32(lib.filter2d_variant_count(B.PATH_BATCHED) + 1)
+    assert lib.filter2d_batched_plan(items, 2, B.F32, 3, ctypes.byref(var), prefix) == -B.EINVAL
 
 
 def test_batched_plan_tags_the_table(lib):

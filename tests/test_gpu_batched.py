@@ -43,7 +43,7 @@ def test_ragged_batch_matches_oracle_and_single_calls(gpu_lib, k):
         assert torch.equal(single, y)
 
 
-@pytest.mark.parametrize("variant", [1, 2, 3, 4])
+@pytest.mark.parametrize("variant", [1, 2, 3, 4, 5, 6, 7, 8])
 def test_ragged_variants_bitwise(gpu_lib, variant):
     xs, fs = _batch(2, 7, SIZES)
     _, _, _, y1 = _run(gpu_lib, xs, fs, variant=1)
@@ -51,6 +51,32 @@ def test_ragged_variants_bitwise(gpu_lib, variant):
     assert batch.variant == variant
     for a, b in zip(y1, yv):
         assert torch.equal(a, b)
+
+
+# Many items with empty ones between them: enough tiles that every
+# work-group of the pipelined (persistent) variants walks several tiles, and
+# its runs cross plane and item boundaries.
+MANY = [(3, 97, 301), (0, 10, 10), (2, 257, 65), (1, 0, 40), (3, 33, 700), (2, 190, 190), (1, 30, 0),
+        (3, 300, 129), (1, 1, 1), (2, 513, 77), (3, 64, 64), (1, 129, 400), (3, 700, 520),
+        (2, 1100, 333)] * 6
+
+
+@pytest.mark.parametrize("k", [3, 9])
+@pytest.mark.parametrize("variant", [5, 6, 7, 8])
+def test_ragged_pipelined_walks_across_items(gpu_lib, variant, k):
+    xs, fs = _batch(6, k, MANY)
+    batch, xd, fd, yd = _run(gpu_lib, xs, fs, variant=variant)
+    assert batch.variant == variant
+    # several tiles per work-group: at most 3 resident work-groups on each of 256 CUs
+    assert batch.total_tiles > 3 * 768
+    for i, (x, f, xdi, fdi, y) in enumerate(zip(xs, fs, xd, fd, yd)):
+        if x.size == 0:
+            continue
+        single = gpu_lib.forward(xdi, fdi, variant=1)[0]
+        assert torch.equal(single, y), i
+        if i < len(MANY) // 6:
+            ref = oracle.forward(x[None], f.astype(np.float64))[0]
+            assert oracle.rel_l2(y.double().cpu().numpy(), ref) <= 1e-5, i
 
 
 def test_ragged_graph_replay_equals_eager(gpu_lib):
@@ -104,7 +130,7 @@ def test_ragged_table_for_another_variant_writes_nothing(gpu_lib):
     fd = [torch.from_numpy(f).cuda() for f in fs]
     yd = [torch.full_like(x, float("nan")) for x in xd]
     batch = gpu_lib.RaggedBatch(xd, yd, fd, variant=2)
-    for variant, k in ((1, 5), (3, 5), (4, 5), (2, 3), (2, 7)):
+    for variant, k in ((1, 5), (3, 5), (4, 5), (6, 5), (8, 5), (2, 3), (2, 7)):
         batch.run(variant=variant, k=k)
         torch.cuda.synchronize()
         assert all(bool(torch.isnan(y).all()) for y in yd), (variant, k)
