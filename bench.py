@@ -612,15 +612,19 @@ TRAFFIC_KERNELS = {
                                 lambda: bank_bytes(5)["fwd_f32out"], BANK_SRC),
     "bank_bf16_k5_dgrad": (lambda n: "k_bank_conv_ring" in n, lambda: bank_bytes(5)["dgrad"], BANK_SRC),
     "bank_bf16_k5_wgrad": (lambda n: "k_bank_wgrad" in n, lambda: bank_bytes(5)["wgrad"], BANK_SRC),
+    # `--profile-sobel`: 8K RGB u8 in, gx, gy, gx^2+gy^2 int32 out
+    "sobel_u8_8k": (lambda n: "k_stencil_u8" in n, lambda: 3 * 4320 * 7680 * (1 + 3 * 4),
+                    ["paper_2504_01266_amd/csrc/stencil_u8.hip"]),
 }
 
 
 def traffic_from(fetch_dir, write_dir):
-    """HBM bytes per launch of the headline kernels from two rocprofv3 counter
-    runs of `bench.py --profile` (FETCH_SIZE, then WRITE_SIZE, in KiB per
-    dispatch), each scaled by what the same counter reads for the run's final
-    1 GiB device copy (whose bytes are known); written to profiles/traffic.json
-    with the kernel sources' hash."""
+    """HBM bytes per launch of the headline kernels and the 8K Sobel from
+    rocprofv3 counter runs of `bench.py --profile` and `--profile-sobel`
+    (FETCH_SIZE runs under fetch_dir, WRITE_SIZE runs under write_dir, in KiB
+    per dispatch), each scaled by what the same counter reads for the runs'
+    final 1 GiB device copy (whose bytes are known); written to
+    profiles/traffic.json with the kernel sources' hash."""
     import csv
     import glob
     import re
