@@ -1194,11 +1194,19 @@ __device__ __forceinline__ bf16x8 g_fragment(const float* src) {
 template <typename TG>
 __device__ __forceinline__ void load_g(const WgradParams& p, const TG* gp, int o, int64_t y0, int64_t xb,
                                        bool fast, bf16x8 (&ga)[kWgTH]) {
+  if (fast && y0 + kWgTH <= p.H) {  // uniform
+    // every row inside the image: plain loads with nothing applied to the
+    // values (a select on each loaded row here made every load wait for the
+    // previous one: 2.84 -> 2.37 ms for the 5x5 bank once removed)
+#pragma unroll
+    for (int m = 0; m < kWgTH; ++m) ga[m] = g_fragment(gp + o * p.g_sc + (y0 + m) * p.g_sh + xb);
+    return;
+  }
 #pragma unroll
   for (int m = 0; m < kWgTH; ++m) {
     const int64_t y = y0 + m;
     if (fast) {
-      // interior tile: every row y < H is loaded (rows past H are zeroed)
+      // rows past H are zeroed
       const int64_t yc = y < p.H ? y : p.H - 1;
       const bf16x8 v = g_fragment(gp + o * p.g_sc + yc * p.g_sh + xb);
       ga[m] = y < p.H ? v : bf16x8{};
