@@ -145,19 +145,54 @@ __global__ __launch_bounds__(kGThreads) void k_u8_gather(GatherParams p) {
       }
       off[k][jj] = inside ? static_cast<int32_t>(div_s(static_cast<uint32_t>(xc), p)) * P + ch : -1;
     }
+  // A window word whose four source bytes lie inside one 8-byte stretch of
+  // the row (everywhere but zeroed border elements and the row's last bytes:
+  // consecutive bytes without upsampling, at most two source pixels with it;
+  // clamped edge pixels may repeat earlier offsets) is one or two 4-byte
+  // loads from its lowest offset and a byte permute, instead of four byte
+  // loads.
+  const int32_t row_len = static_cast<int32_t>(p.W) * P;  // bytes of a source row
+  bool dw[NQ], two_dw[NQ];
+  int32_t dbase[NQ];
+  uint32_t sel[NQ];
+#pragma unroll
+  for (int k = 0; k < NQ; ++k) {
+    int32_t lo = off[k][0], hi = off[k][0];
+#pragma unroll
+    for (int jj = 1; jj < 4; ++jj) {
+      lo = off[k][jj] < lo ? off[k][jj] : lo;
+      hi = off[k][jj] > hi ? off[k][jj] : hi;
+    }
+    const int32_t span = hi - lo;
+    two_dw[k] = span > 3;
+    dw[k] = lo >= 0 && span <= 7 && lo + (two_dw[k] ? 7 : 3) < row_len;
+    dbase[k] = lo < 0 ? 0 : lo;
+    sel[k] = 0;
+#pragma unroll
+    for (int jj = 0; jj < 4; ++jj) sel[k] |= static_cast<uint32_t>((off[k][jj] - lo) & 7) << (8 * jj);
+  }
+  typedef uint32_t u32_unaligned __attribute__((aligned(1)));
   for (int ri = 0; ri < nsrc; ri += 2) {
     const bool two = ri + 1 < nsrc;  // uniform
     const uint8_t* rp0 = sp + static_cast<int64_t>(rlo + ri) * p.s_sh;
     const uint8_t* rp1 = two ? rp0 + p.s_sh : rp0;
     uint32_t b[2][NQ][4];
 #pragma unroll
-    for (int k = 0; k < NQ; ++k)
+    for (int k = 0; k < NQ; ++k) {
+      if (dw[k]) {
+        b[0][k][0] = *reinterpret_cast<const u32_unaligned*>(rp0 + dbase[k]);
+        b[1][k][0] = *reinterpret_cast<const u32_unaligned*>(rp1 + dbase[k]);
+        b[0][k][1] = two_dw[k] ? *reinterpret_cast<const u32_unaligned*>(rp0 + dbase[k] + 4) : 0u;
+        b[1][k][1] = two_dw[k] ? *reinterpret_cast<const u32_unaligned*>(rp1 + dbase[k] + 4) : 0u;
+      } else {
 #pragma unroll
-      for (int jj = 0; jj < 4; ++jj) {
-        const int32_t o = off[k][jj] < 0 ? 0 : off[k][jj];
-        b[0][k][jj] = rp0[o];
-        b[1][k][jj] = rp1[o];
+        for (int jj = 0; jj < 4; ++jj) {
+          const int32_t o = off[k][jj] < 0 ? 0 : off[k][jj];
+          b[0][k][jj] = rp0[o];
+          b[1][k][jj] = rp1[o];
+        }
       }
+    }
 #pragma unroll
     for (int k = 0; k < NQ; ++k) {
       const int q = tid + kGThreads * k;
@@ -165,9 +200,13 @@ __global__ __launch_bounds__(kGThreads) void k_u8_gather(GatherParams p) {
 #pragma unroll
       for (int h = 0; h < 2; ++h) {
         uint32_t w = 0;
+        if (dw[k]) {
+          w = __builtin_amdgcn_perm(b[h][k][1], b[h][k][0], sel[k]);  // bytes 0-3: first load, 4-7: second
+        } else {
 #pragma unroll
-        for (int jj = 0; jj < 4; ++jj)
-          if (off[k][jj] >= 0) w |= b[h][k][jj] << (8 * jj);
+          for (int jj = 0; jj < 4; ++jj)
+            if (off[k][jj] >= 0) w |= b[h][k][jj] << (8 * jj);
+        }
         if (h == 0 || two) lds[(ri + h) * kGPitchWords + q] = w;
       }
     }
