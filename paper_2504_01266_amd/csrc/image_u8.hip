@@ -350,7 +350,7 @@ struct MixParams {
 };
 
 constexpr int kMixThreads = 256;
-constexpr int kMixPx = 4;  // pixels per lane
+constexpr int kMixPx = 16;  // pixels per lane (measured: 8K gray 0.048 ms with 4)
 
 template <int CIN, bool TF, int OUT>
 __global__ __launch_bounds__(kMixThreads) void k_u8_mix(MixParams p) {
@@ -369,9 +369,9 @@ __global__ __launch_bounds__(kMixThreads) void k_u8_mix(MixParams p) {
   uint32_t x[CIN][kMixPx];
   if (p.s_sw == CIN && p.s_sc == 1 && CIN > 1) {  // interleaved
     if (p.in_vec && full) {
-      uint32_t wd[CIN];
+      uint32_t wd[CIN * kMixPx / 4];
 #pragma unroll
-      for (int q = 0; q < CIN; ++q) wd[q] = reinterpret_cast<const uint32_t*>(rp + x0 * CIN)[q];
+      for (int q = 0; q < CIN * kMixPx / 4; ++q) wd[q] = reinterpret_cast<const uint32_t*>(rp + x0 * CIN)[q];
 #pragma unroll
       for (int k = 0; k < kMixPx; ++k)
 #pragma unroll
@@ -390,9 +390,11 @@ __global__ __launch_bounds__(kMixThreads) void k_u8_mix(MixParams p) {
     for (int i = 0; i < CIN; ++i) {
       const uint8_t* cp = rp + i * p.s_sc;
       if (p.in_vec && full) {
-        const uint32_t wd = *reinterpret_cast<const uint32_t*>(cp + x0);
+        uint32_t wd[kMixPx / 4];
 #pragma unroll
-        for (int k = 0; k < kMixPx; ++k) x[i][k] = (wd >> (8 * k)) & 0xffu;
+        for (int q = 0; q < kMixPx / 4; ++q) wd[q] = reinterpret_cast<const uint32_t*>(cp + x0)[q];
+#pragma unroll
+        for (int k = 0; k < kMixPx; ++k) x[i][k] = (wd[k >> 2] >> (8 * (k & 3))) & 0xffu;
       } else {
 #pragma unroll
         for (int k = 0; k < kMixPx; ++k) x[i][k] = x0 + k < p.W ? cp[(x0 + k) * p.s_sw] : 0u;
@@ -432,7 +434,10 @@ __global__ __launch_bounds__(kMixThreads) void k_u8_mix(MixParams p) {
       }
       uint8_t* dp = static_cast<uint8_t*>(p.dst) + obase;
       if (p.out_vec && full && p.d_sw == 1) {
-        *reinterpret_cast<uint32_t*>(dp + x0) = q8[0] | (q8[1] << 8) | (q8[2] << 16) | (q8[3] << 24);
+#pragma unroll
+        for (int q = 0; q < kMixPx / 4; ++q)
+          reinterpret_cast<uint32_t*>(dp + x0)[q] =
+              q8[4 * q] | (q8[4 * q + 1] << 8) | (q8[4 * q + 2] << 16) | (q8[4 * q + 3] << 24);
       } else {
 #pragma unroll
         for (int k = 0; k < kMixPx; ++k)
@@ -441,9 +446,11 @@ __global__ __launch_bounds__(kMixThreads) void k_u8_mix(MixParams p) {
     } else {
       uint32_t* dp = static_cast<uint32_t*>(p.dst) + obase;
       if (p.out_vec && full && p.d_sw == 1) {
-        *reinterpret_cast<uint4*>(dp + x0) =
-            make_uint4(__builtin_bit_cast(uint32_t, acc[0]), __builtin_bit_cast(uint32_t, acc[1]),
-                       __builtin_bit_cast(uint32_t, acc[2]), __builtin_bit_cast(uint32_t, acc[3]));
+#pragma unroll
+        for (int q = 0; q < kMixPx / 4; ++q)
+          reinterpret_cast<uint4*>(dp + x0)[q] =
+              make_uint4(__builtin_bit_cast(uint32_t, acc[4 * q]), __builtin_bit_cast(uint32_t, acc[4 * q + 1]),
+                         __builtin_bit_cast(uint32_t, acc[4 * q + 2]), __builtin_bit_cast(uint32_t, acc[4 * q + 3]));
       } else {
 #pragma unroll
         for (int k = 0; k < kMixPx; ++k)
