@@ -617,9 +617,9 @@ def profile_sobel(torch, B, wl, steps):
 
 TRAFFIC_KERNELS = {
     # key in profiles/traffic.json -> (kernel-name test, algorithmic bytes, sources)
-    "bank_bf16_k5_fwd_f32out": (lambda n: "k_bank_conv" in n and "ring" not in n and "_ws" not in n,
-                                lambda: bank_bytes(5)["fwd_f32out"], BANK_SRC),
-    "bank_bf16_k5_dgrad": (lambda n: "k_bank_conv_ring" in n, lambda: bank_bytes(5)["dgrad"], BANK_SRC),
+    "bank_bf16_k5_fwd_f32out": (lambda n: "k_bank_conv<" in n, lambda: bank_bytes(5)["fwd_f32out"], BANK_SRC),
+    "bank_bf16_k5_dgrad": (lambda n: "k_bank_conv_vr<" in n or "k_bank_conv_ring<" in n,
+                           lambda: bank_bytes(5)["dgrad"], BANK_SRC),
     "bank_bf16_k5_wgrad": (lambda n: "k_bank_wgrad" in n, lambda: bank_bytes(5)["wgrad"], BANK_SRC),
     # `--profile-sobel`: 8K RGB u8 in, gx, gy, gx^2+gy^2 int32 out
     "sobel_u8_8k": (lambda n: "k_stencil_u8" in n, lambda: 3 * 4320 * 7680 * (1 + 3 * 4),

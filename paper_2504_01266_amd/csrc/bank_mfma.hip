@@ -24,6 +24,10 @@
 //  k_bank_conv_ring  the same for 33..64 source channels: a work-group walks
 //                down a column segment keeping the staged rows as a ring, so
 //                every tile after the first stages only its 4 new rows.
+//  k_bank_conv_vr  33..64 source channels into at most 16 outputs (the dgrad
+//                of the 16 -> 64 bank): weights in registers, and each pixel
+//                operand read from LDS feeds the MFMAs of every tile row it
+//                reaches (0.4 operand reads per MFMA at K = 5 against 1.5).
 //  k_bank_conv_ws  the forward from 9..16 to 33..64 channels with BF16 outputs,
 //                with the memory traffic on separate waves: MFMA waves read LDS only,
 //                memory waves stage tiles and store results from LDS.
@@ -730,18 +734,22 @@ __device__ __forceinline__ void ring_plan(const BankParams& p, int64_t ox0, int 
   }
 }
 
-// Loads of the planned units for source rows gy_base + row (clamped).
+// Load of planned unit `it` for source rows gy_base + row (clamped), and of
+// every planned unit.
+template <typename TS, int NTN>
+__device__ __forceinline__ void ring_load_unit(const BankParams& p, const TS* __restrict__ sp_n, int64_t gy_base,
+                                               const RingPlan<NTN>& pl, Raw<TS, NTN>& st, int it) {
+  const int32_t hl = static_cast<int32_t>(p.H) - 1;
+  const uint32_t sh = static_cast<uint32_t>(p.s_sh);
+  int32_t gy = static_cast<int32_t>(gy_base) + static_cast<int32_t>(pl.info[it] & 0xffu);
+  gy = gy < 0 ? 0 : (gy > hl ? hl : gy);
+  load_vec(sp_n + (pl.soff[it] + __umul24(static_cast<uint32_t>(gy), sh)), st.v[it]);
+}
 template <typename TS, int NTN>
 __device__ __forceinline__ void ring_load(const BankParams& p, const TS* __restrict__ sp_n, int64_t gy_base,
                                           const RingPlan<NTN>& pl, Raw<TS, NTN>& st) {
-  const int32_t hl = static_cast<int32_t>(p.H) - 1;
-  const uint32_t sh = static_cast<uint32_t>(p.s_sh);
 #pragma unroll
-  for (int it = 0; it < NTN; ++it) {
-    int32_t gy = static_cast<int32_t>(gy_base) + static_cast<int32_t>(pl.info[it] & 0xffu);
-    gy = gy < 0 ? 0 : (gy > hl ? hl : gy);
-    load_vec(sp_n + (pl.soff[it] + __umul24(static_cast<uint32_t>(gy), sh)), st.v[it]);
-  }
+  for (int it = 0; it < NTN; ++it) ring_load_unit<TS, NTN>(p, sp_n, gy_base, pl, st, it);
 }
 
 // Edge fix, padding, transpose and ring write of planned unit `it` (tile row
@@ -906,6 +914,194 @@ __global__ __launch_bounds__(512) void k_bank_conv_ring(BankParams p) {
         }
         slot = nslot;
       }
+    }
+  }
+}
+
+// ------------------------------------------------- vertical tap reuse --
+//
+// 33..64 source channels into at most 16 output channels: the adjoint of the
+// 16 -> 64 bank (dgrad) and forwards of that shape.  With a single 16-channel
+// output block, a pixel operand that k_bank_conv_ring reads from LDS feeds one
+// MFMA, and with the weight reads that is 1.5 LDS reads of 1 KiB per MFMA: the
+// LDS read port, not the matrix cores, sets the pace there.  Here the weights
+// stay in registers, and a wave walks the staged rows of its tile in source-row
+// order: the operand of staged row s and tap column v feeds the MFMAs of every
+// tile row y it reaches (tap row s - y), so a tile of kTH rows takes LH*K
+// operand reads for kTH*K*K MFMAs per 32 channels (0.4 reads per MFMA at
+// K = 5).  A wave keeps the K*K taps of one 32-channel half of the source
+// channels for its 16 output channels (4*K*K registers); the two halves of the
+// same outputs run in two waves and meet in LDS: each leaves its sums of half
+// the tile rows there and completes and stores the other rows (splitting the
+// stores measured 5% faster at K = 5 than one half storing all).  Eight waves
+// per work-group: two halves x four 16-pixel column blocks, each over all kTH
+// rows of a kTH x 64 tile; the staged rows are kept as a ring as in
+// k_bank_conv_ring, and every load runs a tile ahead of its packing.
+template <int K>
+struct VrGeom : ConvGeom<K, 1, 4, 8, 8> {
+  using Base = ConvGeom<K, 1, 4, 8, 8>;
+  static constexpr int ROWE = Base::LW * Base::PS;  // elements per ring row
+  // partial sums handed between the halves: two buffers (alternate tiles)
+  // of [column block][tile row][lane][4] floats
+  static constexpr int RED_F = 2 * 4 * kTH * 64 * 4;
+  static constexpr bool fits(int slots) { return slots * ROWE * 2 + RED_F * 4 <= 160 * 1024; }
+  // a ring with room for the next tile's kTH new rows where it fits; else LH
+  // rows, the new rows replacing the kTH oldest once every wave is past them
+  static constexpr int NSLOT = fits(Base::LH + kTH) ? Base::LH + kTH : Base::LH;
+  static constexpr int LDS_B = NSLOT * ROWE * 2 + RED_F * 4;
+  static_assert(fits(NSLOT), "ring and sums exceed LDS");
+};
+
+template <int K, bool ADJ, typename TS, bool OUT_BF16>
+__global__ __launch_bounds__(512) void k_bank_conv_vr(BankParams p) {
+  using G = VrGeom<K>;
+  constexpr int LH = G::LH, KK = K * K;
+  constexpr int NG = LH * K;  // (staged row, tap column) operand groups per tile
+  constexpr int NEW = kTH;
+  constexpr bool OVL = G::NSLOT > LH;
+  // groups that read the kTH oldest rows; without room for the new rows in
+  // the ring, a barrier after them frees those rows for the next tile
+  constexpr int SB = kTH * K;
+  constexpr int NTN = staging_nt<G, 8, NEW>();
+  // the next tile's rows are packed unit by unit between the MFMA groups
+  // from group PK0 on (late enough that their loads have landed)
+  constexpr int PK0 = OVL ? NG / 2 : SB;
+  static_assert(LH % NEW == 0 || G::NSLOT >= (LH + NEW - 1) / NEW * NEW, "first rows' last batch inside the ring");
+  extern __shared__ uint4 smem4[];
+  uint16_t* ring = reinterpret_cast<uint16_t*>(smem4);
+  float* red = reinterpret_cast<float*>(ring + G::NSLOT * G::ROWE);
+  const int tid = threadIdx.x;
+  const int lane = tid % 64;
+  const int wave = __builtin_amdgcn_readfirstlane(tid / 64);
+  const int half = wave >> 2;  // source channels 32*half .. 32*half+31
+  const int cb = wave & 3;     // pixels 16*cb .. 16*cb+15 of the tile
+  const int l16 = lane % 16, q = lane / 16;
+  const int lane_off = (16 * cb + l16 + G::XOFF) * G::PS + half * 32 + q * 8;
+  float* red_lane = red + (cb * kTH * 64 + lane) * 4;
+
+  // B operands: output channel l16, source channels 32*half + 8q .. +7 of tap
+  // t, read once from the weights laid out in LDS as k_bank_conv keeps them
+  // (the ring's space is free until the first segment is staged)
+  static_assert(G::W_ELEMS <= G::NSLOT * G::ROWE, "weights staged in the ring space");
+  load_weights<G, K, 1, 8, ADJ, 512>(p, 0, tid, ring);
+  __syncthreads();
+  bf16x8 wr[KK];
+#pragma unroll
+  for (int t = 0; t < KK; ++t)
+    wr[t] = *reinterpret_cast<const bf16x8*>(ring + l16 * G::WSTR + (t * 8 + half * 4 + q) * 8);
+
+  const uint32_t spc = static_cast<uint32_t>(p.seg_per_col), tx = static_cast<uint32_t>(p.tiles_x);
+  uint32_t tcount = 0;
+  // XCD-aware start (see k_bank_conv)
+  for (int64_t sg = xcd_remap(blockIdx.x, gridDim.x); sg < p.n_segs; sg += gridDim.x) {
+    const uint32_t col = static_cast<uint32_t>(sg) / spc, sy = static_cast<uint32_t>(sg) - col * spc;
+    const uint32_t tile_x = col % tx;
+    const int64_t n = col / tx;  // one output group
+    const int ty0 = static_cast<int>(sy) * p.seg_len;
+    const int ty1 = ty0 + p.seg_len < p.tiles_y ? ty0 + p.seg_len : p.tiles_y;
+    const int64_t ox0 = (ADJ ? p.col0 : 0) + static_cast<int64_t>(tile_x) * G::TW;
+    __syncthreads();  // every wave is done with the ring and sums of the previous segment
+    const TS* sp_n = static_cast<const TS*>(p.src) + n * p.s_sn;
+    Raw<TS, NTN> st;
+    RingPlan<NTN> pl;
+    ring_plan<G, 8, NEW, NTN>(p, ox0, wave, lane, pl);
+    // the segment's first LH rows into ring rows 0 .. LH-1, NEW rows at a
+    // time with the tile loop's plan (the weights already hold 4*K*K
+    // registers); a last partial batch also fills ring rows past LH, which
+    // the first tile's new rows overwrite later
+    for (int b = 0; b < (LH + NEW - 1) / NEW; ++b) {
+      const int64_t gyb = p.row0 + static_cast<int64_t>(ty0) * kTH - G::R + b * NEW;
+      ring_load<TS, NTN>(p, sp_n, gyb, pl, st);
+      int s0 = b * NEW - (LH - NEW);
+      s0 += s0 < 0 ? G::NSLOT : 0;
+#pragma unroll
+      for (int u = 0; u < NTN; ++u) ring_store_unit<G, ADJ, TS, NEW, NTN>(p, gyb, lane, pl, st, ring, u, s0);
+    }
+    int slot = 0;
+    // the second tile's new rows, packed during the first tile
+    ring_load<TS, NTN>(p, sp_n, p.row0 + static_cast<int64_t>(ty0) * kTH + kTH - G::R + (LH - NEW), pl, st);
+    __syncthreads();
+    // Loads run a tile ahead of their packing: as soon as a unit of the next
+    // tile's rows is packed, its registers are reloaded with the same unit of
+    // the rows after them, so every load has a whole tile to land.  Every
+    // tile, the last of a segment too, loads and packs (rows clamped to the
+    // image, so always valid; the spare ones are never read): with no
+    // condition between the loads and their uses, the compiler's wait counts
+    // stay exact across iterations.
+    for (int ty = ty0; ty < ty1; ++ty) {
+      const int64_t oy0 = static_cast<int64_t>(ty) * kTH;
+      const int64_t gy_next = p.row0 + oy0 + kTH - G::R + (LH - NEW);
+      __builtin_amdgcn_sched_barrier(0);
+      int nslot = slot + NEW;
+      nslot -= nslot >= G::NSLOT ? G::NSLOT : 0;
+      const uint16_t* rl = ring + lane_off;
+      auto operand = [&](auto gi) __attribute__((always_inline)) {
+        constexpr int g = decltype(gi)::value, s = g / K, dx = g % K;
+        int r = slot + s;
+        r -= r >= G::NSLOT ? G::NSLOT : 0;
+        return *reinterpret_cast<const bf16x8*>(rl + r * G::ROWE + dx * G::PS);
+      };
+      f32x4 acc[kTH];
+#pragma unroll
+      for (int y = 0; y < kTH; ++y) acc[y] = f32x4{0.f, 0.f, 0.f, 0.f};
+      bf16x8 xf[3];
+      xf[0] = operand(std::integral_constant<int, 0>{});
+      if constexpr (NG > 1) xf[1] = operand(std::integral_constant<int, 1>{});
+      static_for<NG>([&](auto gi) __attribute__((always_inline)) {
+        constexpr int g = decltype(gi)::value, s = g / K, dx = g % K;
+        if constexpr (g + 2 < NG) xf[(g + 2) % 3] = operand(std::integral_constant<int, g + 2>{});
+        __builtin_amdgcn_sched_barrier(0);
+        constexpr int y0 = s - (K - 1) > 0 ? s - (K - 1) : 0;
+        constexpr int y1 = s < kTH - 1 ? s : kTH - 1;
+#pragma unroll
+        for (int y = y0; y <= y1; ++y)
+          acc[y] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(xf[g % 3], wr[(s - y) * K + dx], acc[y], 0, 0, 0);
+        if constexpr (!OVL && g == SB - 1) __syncthreads();  // the kTH oldest rows are free
+        if constexpr (g >= PK0) {
+          constexpr int u0 = ((g - PK0) * NTN + (NG - PK0) - 1) / (NG - PK0);
+          constexpr int u1 = ((g - PK0 + 1) * NTN + (NG - PK0) - 1) / (NG - PK0);
+#pragma unroll
+          for (int u = u0; u < u1; ++u) {
+            ring_store_unit<G, ADJ, TS, NEW, NTN>(p, gy_next, lane, pl, st, ring, u, nslot);
+            ring_load_unit<TS, NTN>(p, sp_n, gy_next + kTH, pl, st, u);
+          }
+        }
+        __builtin_amdgcn_sched_barrier(0);
+      });
+      // each half completes and stores half of the tile rows: half 0 rows
+      // 0 .. kTH/2-1, half 1 the others; each leaves its sums of the other
+      // rows in LDS for the other half
+      float* rb = red_lane + (tcount & 1u) * (G::RED_F / 2);
+      constexpr int HR = kTH / 2;
+      const int mine = half * HR, theirs = HR - mine;
+#pragma unroll
+      for (int y = 0; y < HR; ++y) *reinterpret_cast<f32x4*>(rb + (theirs + y) * 256) = half ? acc[y] : acc[HR + y];
+      __syncthreads();  // partial sums in LDS; the next tile's rows are packed
+      {
+        f32x4 v[HR];
+#pragma unroll
+        for (int y = 0; y < HR; ++y) v[y] = (half ? acc[HR + y] : acc[y]) + *reinterpret_cast<const f32x4*>(rb + (mine + y) * 256);
+        const int64_t oxw = ox0 + 16 * cb, ya = oy0 + mine, yb = ya + HR - 1;
+        const int64_t iya = ADJ ? p.row0 + ya : ya, iyb = ADJ ? p.row0 + yb : yb;
+        const bool all_fast = p.d_vec && yb < p.rows && (!ADJ || (iya >= 0 && iyb < p.H && oxw >= 0)) &&
+                              oxw + 16 <= p.W;
+        if (all_fast) {  // uniform
+          if (l16 < p.CO) {
+            const int64_t base = n * p.d_sn + static_cast<int64_t>(l16) * p.d_sc + iya * p.d_sh + oxw + 4 * q;
+#pragma unroll
+            for (int y = 0; y < HR; ++y) store4<OUT_BF16>(p.dst, base + y * p.d_sh, v[y]);
+          }
+        } else {
+#pragma unroll
+          for (int y = 0; y < HR; ++y) {
+            f32x4 w[1][1];
+            w[0][0] = v[y];
+            store_acc<ADJ, OUT_BF16, 1, 1>(p, n, l16, ya + y, oxw, q, w);
+          }
+        }
+      }
+      ++tcount;
+      slot = nslot;
     }
   }
 }
@@ -1368,6 +1564,70 @@ __global__ __launch_bounds__(kThreads) __attribute__((amdgpu_waves_per_eu(2))) v
 
 // ------------------------------------------------------------- dispatch --
 
+// Column segments for the row-ring kernels: at most 32 tile rows, at least
+// ~4 per work-group when the columns allow, equal length within a column.
+// False when there is nothing to do.
+bool plan_segments(BankParams& p, int grid) {
+  const int64_t cols = p.n_img * p.o_groups * static_cast<int64_t>(p.tiles_x);
+  if (cols <= 0 || p.tiles_y <= 0) return false;
+  int64_t spc = (p.tiles_y + 31) / 32;
+  const int64_t want = (4 * static_cast<int64_t>(grid) + cols - 1) / cols;
+  if (want > spc) spc = want < p.tiles_y ? want : p.tiles_y;
+  const int64_t len = (p.tiles_y + spc - 1) / spc;
+  p.seg_len = static_cast<int32_t>(len);
+  p.seg_per_col = static_cast<int32_t>((p.tiles_y + len - 1) / len);
+  p.n_segs = cols * p.seg_per_col;
+  return true;
+}
+
+// Resident work-groups of `kern` on the current device (cached per device by
+// the caller's statics).
+hipError_t resident_groups(const void* kern, int threads, size_t lds, int* grid) {
+  int dev = 0;
+  hipError_t e = hipGetDevice(&dev);
+  if (e != hipSuccess) return e;
+  e = hipFuncSetAttribute(kern, hipFuncAttributeMaxDynamicSharedMemorySize, static_cast<int>(lds));
+  if (e != hipSuccess) return e;
+  int per_cu = 0, cus = 0;
+  e = hipOccupancyMaxActiveBlocksPerMultiprocessor(&per_cu, kern, threads, lds);
+  if (e != hipSuccess) return e;
+  e = hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, dev);
+  if (e != hipSuccess) return e;
+  *grid = (per_cu > 0 ? per_cu : 1) * (cus > 0 ? cus : 1);
+  return hipSuccess;
+}
+
+// 33..64 source channels into at most 16 outputs: k_bank_conv_vr
+template <int K, bool ADJ, typename TS, bool OB>
+hipError_t conv_vr_go(const BankParams& pin, hipStream_t s) {
+  using G = VrGeom<K>;
+  BankParams p = pin;
+  if (p.CO > 16 || p.CI > 64 || p.o_groups != 1 || !p.s_plan32) return hipErrorNotSupported;
+  p.tiles_x = static_cast<int32_t>((p.cols + G::TW - 1) / G::TW);
+  p.n_tiles = p.n_img * static_cast<int64_t>(p.tiles_x) * p.tiles_y;
+  const size_t lds = G::LDS_B;
+  const void* kern = reinterpret_cast<const void*>(k_bank_conv_vr<K, ADJ, TS, OB>);
+  static std::mutex mu;
+  static int dev_cached = -1, grid_cached = 0;
+  int dev = 0;
+  hipError_t e = hipGetDevice(&dev);
+  if (e != hipSuccess) return e;
+  int grid;
+  {
+    std::lock_guard<std::mutex> lk(mu);
+    if (dev_cached != dev) {
+      e = resident_groups(kern, 512, lds, &grid_cached);
+      if (e != hipSuccess) return e;
+      dev_cached = dev;
+    }
+    grid = grid_cached;
+  }
+  if (!plan_segments(p, grid)) return hipSuccess;
+  const int64_t g = p.n_segs < grid ? p.n_segs : grid;
+  hipLaunchKernelGGL((k_bank_conv_vr<K, ADJ, TS, OB>), dim3(static_cast<uint32_t>(g)), dim3(512), lds, s, p);
+  return hipGetLastError();
+}
+
 template <int K, int OT, int PT, int CG, int NW, bool ADJ, typename TS, bool OB>
 hipError_t conv_go(const BankParams& pin, hipStream_t s) {
   using G = ConvGeom<K, OT, PT, CG, NW>;
@@ -1404,17 +1664,7 @@ hipError_t conv_go(const BankParams& pin, hipStream_t s) {
     grid = grid_cached;
   }
   if constexpr (RING) {
-    // segments of at most 32 tile rows, at least ~4 per work-group when the
-    // columns allow, equal length within a column
-    const int64_t cols = p.n_img * p.o_groups * static_cast<int64_t>(p.tiles_x);
-    if (cols <= 0 || p.tiles_y <= 0) return hipSuccess;
-    int64_t spc = (p.tiles_y + 31) / 32;
-    const int64_t want = (4 * static_cast<int64_t>(grid) + cols - 1) / cols;
-    if (want > spc) spc = want < p.tiles_y ? want : p.tiles_y;
-    const int64_t len = (p.tiles_y + spc - 1) / spc;
-    p.seg_len = static_cast<int32_t>(len);
-    p.seg_per_col = static_cast<int32_t>((p.tiles_y + len - 1) / len);
-    p.n_segs = cols * p.seg_per_col;
+    if (!plan_segments(p, grid)) return hipSuccess;
     const int64_t g = p.n_segs < grid ? p.n_segs : grid;
     hipLaunchKernelGGL((k_bank_conv_ring<K, OT, PT, CG, ADJ, TS, OB>), dim3(static_cast<uint32_t>(g)),
                        dim3(G::THREADS), lds, s, p);
@@ -1467,6 +1717,17 @@ hipError_t conv_ws_go(const BankParams& pin, hipStream_t s) {
   return hipGetLastError();
 }
 
+// 33..64 source channels, one 16-channel output block per pass: the
+// vertical-reuse kernel for at most 16 outputs from BF16 sources with planned
+// staging, else the row-ring kernel
+template <int K, bool ADJ, typename TS, bool OB>
+hipError_t conv_wide_go(const BankParams& p, hipStream_t s) {
+  if constexpr (std::is_same<TS, uint16_t>::value) {
+    if (p.s_plan32 && p.CO <= 16) return conv_vr_go<K, ADJ, TS, OB>(p, s);
+  }
+  return conv_go<K, 1, 4, 8, 8, ADJ, TS, OB>(p, s);
+}
+
 template <int K, bool ADJ, typename TS, bool OB>
 hipError_t conv_by_shape(const BankParams& p, int ot, int cg, hipStream_t s) {
   // instantiated (OT, CG) pairs, eight waves; 64-pixel tile rows (PT = 4),
@@ -1494,9 +1755,9 @@ hipError_t conv_by_shape(const BankParams& p, int ot, int cg, hipStream_t s) {
     }
     if (ot == 1 && cg == 1) return conv_go<K, 1, 4, 1, 8, ADJ, TS, OB>(p, s);
     if (ot == 1 && cg == 2) return conv_go<K, 1, 4, 2, 8, ADJ, TS, OB>(p, s);
-    if (ot == 1 && cg == 8) return conv_go<K, 1, 4, 8, 8, ADJ, TS, OB>(p, s);
+    if (ot == 1 && cg == 8) return conv_wide_go<K, ADJ, TS, OB>(p, s);
   } else {
-    if (ot == 1 && cg == 8) return conv_go<K, 1, 4, 8, 8, ADJ, TS, OB>(p, s);
+    if (ot == 1 && cg == 8) return conv_wide_go<K, ADJ, TS, OB>(p, s);
     if (ot == 1 && cg == 4) return conv_go<K, 1, 4, 4, 8, ADJ, TS, OB>(p, s);
     if (ot == 1 && cg == 2) return conv_go<K, 1, 4, 2, 8, ADJ, TS, OB>(p, s);
     if (ot == 1 && cg == 1) return conv_go<K, 1, 4, 1, 8, ADJ, TS, OB>(p, s);

@@ -190,6 +190,38 @@ def test_bf16_output_into_unaligned_view(gpu_lib, k):
     assert torch.equal(outside, torch.full_like(big, 7.0))
 
 
+@pytest.mark.parametrize("k", [1, 3, 5])
+def test_wide_source_kernels_bit_exact(gpu_lib, k):
+    """33..64 source channels with aligned rows (W a multiple of 8), where the
+    kernel choice depends on the output count and the source type: 64 -> 16
+    forwards and grad_input from a BF16 upstream gradient take the
+    vertical-reuse kernel (also with 9 outputs, padded to 16), a 40 -> 20
+    forward and grad_input from an FP32 upstream gradient the row-ring kernel.
+    Ragged bottom tiles and edge columns; integer operands, bit-exact (several
+    tiles per column segment: test_row_ring_segments_bit_exact)."""
+    r = wl.rng(43, k)
+    h, w = 45, 136
+    x16 = r.integers(-4, 5, (2, 16, h, w)).astype(np.float32)
+    f = r.integers(-4, 5, (64, 16, k, k)).astype(np.float32)
+    g = r.integers(-4, 5, (2, 64, h, w)).astype(np.float32)
+    xd, _ = bf(x16)
+    fd, fv = bf(f)
+    gd, gv = bf(g)
+    want = oracle.grad_input(gv, fv, x16.shape, "bank")
+    for gdev in (gd, f32(g)):
+        gi, _ = gpu_lib.backward(xd, fd, gdev, mode="bank", need_filter=False)
+        assert_same(host(gi), want)
+    for cin, cout in ((64, 16), (40, 20), (64, 9)):
+        x = r.integers(-4, 5, (2, cin, h, w)).astype(np.float32)
+        ff = r.integers(-4, 5, (cout, cin, k, k)).astype(np.float32)
+        xdd, xv = bf(x)
+        ffd, ffv = bf(ff)
+        ref = oracle.forward(xv, ffv, "bank")
+        assert_same(host(gpu_lib.forward(xdd, ffd, mode="bank")), ref)
+        yb = gpu_lib.forward(xdd, ffd, mode="bank", out_dtype=torch.bfloat16)
+        assert_same(host(yb), wl.bf16_round(ref.astype(np.float32))[1].astype(np.float64))
+
+
 @pytest.mark.parametrize("k", [3, 5])
 def test_row_ring_segments_bit_exact(gpu_lib, k):
     """64-channel sources (grad_input of a 16 -> 64 bank, and a 64 -> 16
