@@ -222,6 +222,45 @@ def test_wide_source_kernels_bit_exact(gpu_lib, k):
         assert_same(host(yb), wl.bf16_round(ref.astype(np.float32))[1].astype(np.float64))
 
 
+@pytest.mark.parametrize("k", [1, 3, 5])
+@pytest.mark.parametrize("hw", [(1, 8), (2, 16), (5, 8), (3, 72), (9, 64)])
+def test_wide_source_tiny_images_bit_exact(gpu_lib, k, hw):
+    """The vertical-reuse kernel (64 -> 16 forward, grad_input from 64 BF16
+    channels) on images shorter than its staged rows and narrower than a tile,
+    where every row is a clamped (forward) or zeroed (adjoint) border row."""
+    h, w = hw
+    r = wl.rng(44, k, h, w)
+    x = r.integers(-4, 5, (2, 64, h, w)).astype(np.float32)
+    f = r.integers(-4, 5, (16, 64, k, k)).astype(np.float32)
+    xd, xv = bf(x)
+    fd, fv = bf(f)
+    assert_same(host(gpu_lib.forward(xd, fd, mode="bank")), oracle.forward(xv, fv, "bank"))
+    x16 = r.integers(-4, 5, (2, 16, h, w)).astype(np.float32)
+    f2 = r.integers(-4, 5, (64, 16, k, k)).astype(np.float32)
+    g = r.integers(-4, 5, (2, 64, h, w)).astype(np.float32)
+    f2d, f2v = bf(f2)
+    gd, gv = bf(g)
+    gi, _ = gpu_lib.backward(bf(x16)[0], f2d, gd, mode="bank", need_filter=False)
+    assert_same(host(gi), oracle.grad_input(gv, f2v, x16.shape, "bank"))
+
+
+def test_wide_source_rows_band(gpu_lib):
+    """64 -> 16 forward in row bands (the vertical-reuse kernel with a band's
+    row offset and count) equals the whole-image call bitwise."""
+    k = 5
+    r = wl.rng(45)
+    x = r.standard_normal((1, 64, 61, 64), dtype=np.float32)
+    f = r.standard_normal((16, 64, k, k), dtype=np.float32) * np.float32(0.03)
+    xd, _ = bf(x)
+    fd, _ = bf(f)
+    whole = gpu_lib.forward(xd, fd, mode="bank")
+    parts = []
+    for y0, y1 in [(0, 9), (9, 30), (30, 61)]:
+        lo, hi = max(0, y0 - 2), min(61, y1 + 2)
+        parts.append(gpu_lib.forward(xd[:, :, lo:hi], fd, mode="bank", rows=(y0 - lo, y1 - lo)))
+    assert torch.equal(torch.cat(parts, dim=2), whole)
+
+
 @pytest.mark.parametrize("k", [3, 5])
 def test_row_ring_segments_bit_exact(gpu_lib, k):
     """64-channel sources (grad_input of a 16 -> 64 bank, and a 64 -> 16
