@@ -182,13 +182,23 @@ f2d_status run_backward(const Problem& pr, const f2d_tensor* grad_outs, int32_t 
       p.frame = static_cast<float*>(ws);
       p.frame_plane = frame_plane_size(im.h, im.w, r);
     }
+    // bank: four image channels per work-group (each staged G-bar tile then
+    // serves four outputs instead of one) where the taps fit in registers
+    const int nout = templ && pr.mode == F2D_CH_BANK && K <= 5 && im.c % 4 == 0 ? 4 : 1;
+    if (nout == 4) {
+      p.groups = static_cast<int32_t>(im.c / 4);
+      p.fg = 4;
+      p.fj = 1;
+      p.dc_g = 4;
+      p.dc_j = 1;
+    }
     const int64_t wext = im.w + (templ ? 2 * r : 0);
     p.tiles_x = static_cast<int32_t>((wext + ts.tw - 1) / ts.tw);
     p.tiles_y = static_cast<int32_t>((p.rows + ts.th - 1) / ts.th);
     p.n_blocks = im.n * p.groups * static_cast<int64_t>(p.tiles_x) * p.tiles_y;
     if (p.n_blocks > kMaxBlocks) return fail(F2D_EUNSUPPORTED, "image too large for one launch");
     if (!templ) p.flags |= kFlip | kZeroBorder;
-    hipError_t err = launch_stencil_f32(p, K, 1, true, templ ? 1 : -1, s);
+    hipError_t err = launch_stencil_f32(p, K, nout, true, templ ? 1 : -1, s);
     if (err != hipSuccess) return hip_status(err, "grad_input launch");
     if (templ) {
       FoldParams fo;
@@ -245,7 +255,15 @@ f2d_status run_backward(const Problem& pr, const f2d_tensor* grad_outs, int32_t 
       q.tiles_y = fp.tiles_y;
       q.tiles_per_unit = fp.tpu;
       if (fp.n_units > kMaxBlocks) return fail(F2D_EUNSUPPORTED, "too many grad_filter work units");
-      hipError_t err = K <= 9 ? launch_grad_filter_f32(q, K, s) : launch_grad_filter_generic(q, K, s);
+      int no = 1, ni = 1;
+      hipError_t err;
+      if (grad_filter_bank_groups(pr.mode, K, pr.c_out, im.c, &no, &ni)) {
+        // filter groups: same partial slots, NO * NI pairs per work-group
+        q.n_units = fp.nrep * fp.chunks * (pr.c_out / no) * (im.c / ni);
+        err = launch_grad_filter_bank_f32(q, K, s);
+      } else {
+        err = K <= 9 ? launch_grad_filter_f32(q, K, s) : launch_grad_filter_generic(q, K, s);
+      }
       if (err != hipSuccess) return hip_status(err, "grad_filter launch");
     }
     hipError_t err = launch_reduce_partials(partial, grad_filter, fp.nf, K * K, fp.nrep,

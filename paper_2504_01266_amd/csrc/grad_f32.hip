@@ -278,6 +278,132 @@ __global__ __launch_bounds__(kThreads) void k_grad_filter_f32(GradFilterParams p
   }
 }
 
+// Filter banks: a work-group takes NO G-bar planes (output channels
+// NO*og ..) and NI X planes (input channels NI*ig ..) of one image over a run
+// of tiles, so that every staged X tile serves NO output channels and every
+// G-bar block NI input channels (one plane pair per work-group reads each X
+// plane C_out times and each G-bar plane C_in times).  Per filter pair the
+// sums run in the same order as in k_grad_filter_f32, and the partials land
+// in the same workspace slots, so the results are the same bits.
+template <int K, int NO, int NI>
+__global__ __launch_bounds__(kThreads) void k_grad_filter_bank_f32(GradFilterParams p) {
+  using G = Geom<K, kGfPX, kGfPY>;
+  constexpr int KK = K * K;
+  __shared__ float4 lds4[NI][(G::LDS_WORDS + 3) / 4];
+  __shared__ float red[kThreads / 64][NO * NI * KK];
+
+  const int64_t co = p.nf / p.C;
+  const int64_t ngo = co / NO, ngi = p.C / NI;
+  // output-channel group fastest: consecutive work-groups (one XCD) share
+  // their X tiles, and the G-bar tiles recur every ngo*chunks groups
+  int64_t rest = xcd_remap(blockIdx.x, p.n_units);
+  const int64_t og = rest % ngo;
+  rest /= ngo;
+  const int64_t chunk = rest % p.chunks;
+  rest /= p.chunks;
+  const int64_t ig = rest % ngi;
+  const int64_t n = rest / ngi;
+  const float* xp[NI];
+#pragma unroll
+  for (int k = 0; k < NI; ++k)
+    xp[k] = static_cast<const float*>(p.x) + n * p.x_sn + (ig * NI + k) * p.x_sc;
+  const float* gp[NO];
+  int64_t gsh = 0;
+#pragma unroll
+  for (int j = 0; j < NO; ++j) gp[j] = gbar_plane(p, 0, n, og * NO + j, gsh);
+
+  float acc[NO][NI][KK];
+#pragma unroll
+  for (int j = 0; j < NO; ++j)
+#pragma unroll
+    for (int k = 0; k < NI; ++k)
+#pragma unroll
+      for (int e = 0; e < KK; ++e) acc[j][k][e] = 0.0f;
+  const int tx = threadIdx.x % kTX, ty = threadIdx.x / kTX;
+  const int64_t tiles = static_cast<int64_t>(p.tiles_x) * p.tiles_y;
+  for (int tt = 0; tt < p.tiles_per_unit; ++tt) {
+    const int64_t tile = chunk * p.tiles_per_unit + tt;
+    if (tile >= tiles) break;
+    const int64_t oy0 = (tile / p.tiles_x) * G::TH, ox0 = (tile % p.tiles_x) * G::TW;
+#pragma unroll
+    for (int k = 0; k < NI; ++k)
+      stage_tile<K, kGfPX, kGfPY, false>(reinterpret_cast<float*>(lds4[k]), xp[k], p.x_sh, p.H, p.W, oy0, ox0);
+    float gv[NO][kGfPY][kGfPX];
+#pragma unroll
+    for (int j = 0; j < NO; ++j)
+#pragma unroll
+      for (int jy = 0; jy < kGfPY; ++jy) {
+        const int64_t y = oy0 + ty * kGfPY + jy;
+        const int64_t x = ox0 + tx * kGfPX;
+        const float* row = gp[j] + (y < p.H ? y : 0) * gsh;
+        if ((p.flags & kDstVec) && y < p.H && x + kGfPX <= p.W) {
+          const float4 q = *reinterpret_cast<const float4*>(row + x);
+          gv[j][jy][0] = q.x;
+          gv[j][jy][1] = q.y;
+          gv[j][jy][2] = q.z;
+          gv[j][jy][3] = q.w;
+        } else {
+#pragma unroll
+          for (int px = 0; px < kGfPX; ++px)
+            gv[j][jy][px] = (y < p.H && x + px < p.W) ? row[x + px] : 0.0f;
+        }
+      }
+    __syncthreads();
+#pragma unroll
+    for (int k = 0; k < NI; ++k) {
+      const float* lds = reinterpret_cast<const float*>(lds4[k]);
+#pragma unroll
+      for (int ry = 0; ry < kGfPY + K - 1; ++ry) {
+        float win[G::WIN4];
+        const float4* rowp = reinterpret_cast<const float4*>(lds + (ty * kGfPY + ry) * G::PITCH + tx * kGfPX);
+#pragma unroll
+        for (int q = 0; q < G::WIN4 / 4; ++q) {
+          const float4 t = rowp[q];
+          win[4 * q + 0] = t.x;
+          win[4 * q + 1] = t.y;
+          win[4 * q + 2] = t.z;
+          win[4 * q + 3] = t.w;
+        }
+#pragma unroll
+        for (int j = 0; j < NO; ++j)
+#pragma unroll
+          for (int jy = 0; jy < kGfPY; ++jy) {
+            const int u = ry - jy;
+            if (u < 0 || u >= K) continue;
+#pragma unroll
+            for (int v = 0; v < K; ++v)
+#pragma unroll
+              for (int px = 0; px < kGfPX; ++px)
+                acc[j][k][u * K + v] = __builtin_fmaf(gv[j][jy][px], win[px + v], acc[j][k][u * K + v]);
+          }
+      }
+    }
+    __syncthreads();
+  }
+  // the same fixed-order reduction as k_grad_filter_f32, per filter pair
+  const int lane = threadIdx.x % 64, wave = threadIdx.x / 64;
+#pragma unroll
+  for (int j = 0; j < NO; ++j)
+#pragma unroll
+    for (int k = 0; k < NI; ++k)
+#pragma unroll
+      for (int e = 0; e < KK; ++e) {
+        float v = acc[j][k][e];
+#pragma unroll
+        for (int off = 32; off >= 1; off >>= 1) v += __shfl_xor(v, off, 64);
+        if (lane == 0) red[wave][(j * NI + k) * KK + e] = v;
+      }
+  __syncthreads();
+  for (int idx = threadIdx.x; idx < NO * NI * KK; idx += kThreads) {
+    float sum = red[0][idx];
+#pragma unroll
+    for (int w = 1; w < kThreads / 64; ++w) sum += red[w][idx];
+    const int jk = idx / KK, e = idx - jk * KK;
+    const int64_t f = (og * NO + jk / NI) * p.C + ig * NI + jk % NI;
+    p.partial[((n * p.nf + f) * p.chunks + chunk) * KK + e] = sum;
+  }
+}
+
 // Runtime-K fallback (K > 9): one tap at a time, every thread summing its
 // pixels of the unit's tiles straight from memory, then the same fixed-order
 // block reduction.
@@ -427,6 +553,28 @@ hipError_t launch_grad_filter_f32(const GradFilterParams& p, int K, hipStream_t 
     case 5: hipLaunchKernelGGL(k_grad_filter_f32<5>, grid, block, 0, s, p); break;
     case 7: hipLaunchKernelGGL(k_grad_filter_f32<7>, grid, block, 0, s, p); break;
     case 9: hipLaunchKernelGGL(k_grad_filter_f32<9>, grid, block, 0, s, p); break;
+    default: return hipErrorInvalidValue;
+  }
+  return hipGetLastError();
+}
+
+// Filter pairs per work-group of the grouped bank kernel: NO output x NI
+// input channels for K = 1, 3 (4 x 4) and 5 (2 x 2); false where it does not
+// apply (other modes or K, or channel counts that the groups do not divide).
+bool grad_filter_bank_groups(int mode, int K, int64_t co, int64_t ci, int* no, int* ni) {
+  *no = K <= 3 ? 4 : 2;
+  *ni = K <= 3 ? 4 : 2;
+  return mode == F2D_CH_BANK && (K == 1 || K == 3 || K == 5) && co % *no == 0 && ci % *ni == 0;
+}
+
+// p.n_units = images * chunks * (C_out / NO) * (C_in / NI)
+hipError_t launch_grad_filter_bank_f32(const GradFilterParams& p, int K, hipStream_t s) {
+  if (p.n_units <= 0) return hipSuccess;
+  const dim3 grid(static_cast<uint32_t>(p.n_units)), block(kThreads);
+  switch (K) {
+    case 1: hipLaunchKernelGGL((k_grad_filter_bank_f32<1, 4, 4>), grid, block, 0, s, p); break;
+    case 3: hipLaunchKernelGGL((k_grad_filter_bank_f32<3, 4, 4>), grid, block, 0, s, p); break;
+    case 5: hipLaunchKernelGGL((k_grad_filter_bank_f32<5, 2, 2>), grid, block, 0, s, p); break;
     default: return hipErrorInvalidValue;
   }
   return hipGetLastError();

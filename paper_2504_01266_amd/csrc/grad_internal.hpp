@@ -57,6 +57,8 @@ constexpr int kEdgeF32 = 0;
 hipError_t launch_grad_input_edges(const EdgeParams& p, int kind, hipStream_t s);
 hipError_t launch_grad_filter_f32(const GradFilterParams& p, int K, hipStream_t s);
 hipError_t launch_grad_filter_generic(const GradFilterParams& p, int K, hipStream_t s);
+bool grad_filter_bank_groups(int mode, int K, int64_t co, int64_t ci, int* no, int* ni);
+hipError_t launch_grad_filter_bank_f32(const GradFilterParams& p, int K, hipStream_t s);
 // Sums the partials over items (rep, chunk) in a fixed order; overwrites
 // some partial slots with intermediate sums.
 hipError_t launch_reduce_partials(float* partial, float* out, int64_t nf, int kk, int64_t nrep,

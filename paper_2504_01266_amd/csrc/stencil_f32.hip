@@ -55,15 +55,17 @@ __device__ __forceinline__ void store_outputs(const StencilParams& p, int64_t n,
 // Image adjoint store: image coordinates (iy, ix) = (row0 + oy, ox); pixels
 // inside the image go to the output plane, pixels on the r-wide frame to the
 // frame buffer (folded onto the edge pixels afterwards).
+// Output j of a group is channel g*dc_g + j*dc_j of groups*dc_g per image.
 template <int PX, int PY>
-__device__ __forceinline__ void store_adjoint(const StencilParams& p, int64_t n, int64_t g, int64_t oy0,
+__device__ __forceinline__ void store_adjoint(const StencilParams& p, int64_t n, int64_t g, int j, int64_t oy0,
                                               int64_t ox0, const float (&acc)[PY][PX]) {
   const bool vec = (p.flags & kDstVec) != 0;
   const int tx = threadIdx.x % kTX;
   const int ty = threadIdx.x / kTX;
   int64_t dsh;
-  float* dp = dst_fixed<0>(p, n, g * p.dc_g, dsh);
-  float* fp = p.frame + (n * p.groups + g) * p.frame_plane;
+  const int64_t ch = g * p.dc_g + j * p.dc_j;
+  float* dp = dst_fixed<0>(p, n, ch, dsh);
+  float* fp = p.frame + (n * p.groups * p.dc_g + ch) * p.frame_plane;
   const int64_t r = p.fr;
 #pragma unroll
   for (int jy = 0; jy < PY; ++jy) {
@@ -140,9 +142,10 @@ __global__ __launch_bounds__(kThreads) void k_stencil_f32(StencilParams p) {
     __syncthreads();
   }
 
-  if constexpr (ADJ)
-    store_adjoint<PX, PY>(p, n, g, oy0, ox0, acc[0]);
-  else
+  if constexpr (ADJ) {
+#pragma unroll
+    for (int j = 0; j < NOUT; ++j) store_adjoint<PX, PY>(p, n, g, j, oy0, ox0, acc[j]);
+  } else
     store_outputs<NOUT, PX, PY>(p, n, g, oy0, ox0, acc);
 }
 
@@ -237,6 +240,10 @@ template <int K>
 hipError_t by_nout(const StencilParams& p, int nout, bool adj, int variant, hipStream_t stream) {
   if (adj) {
     if (p.st_s != 0) return go<K, 1, true, 4, 4, true>(p, stream);
+    if (nout == 4) {  // bank adjoint: four image channels per work-group
+      if constexpr (4 * K * K <= kMaxTaps) return by_variant<K, 4, true>(p, 1, stream);
+      return hipErrorInvalidValue;
+    }
     return by_variant<K, 1, true>(p, 1, stream);
   }
   switch (nout) {

@@ -65,6 +65,28 @@ def test_bank_backward_f32(gpu_lib, cout, k):
     assert rel(gf, oracle.grad_filter(x, g, f.shape, "bank")) <= TOL
 
 
+@pytest.mark.parametrize("cio", [(4, 8), (8, 12), (6, 8), (4, 6)])
+@pytest.mark.parametrize("k", [1, 3, 5])
+def test_bank_backward_f32_channel_groups(gpu_lib, cio, k):
+    """FP32 banks whose channel counts the grouped kernels divide: grad_input
+    with four image channels per work-group (C_in % 4 == 0, K <= 5) and
+    grad_filter with 4 x 4 (K <= 3) or 2 x 2 (K = 5) filter pairs per
+    work-group; (6, 8) and (4, 6) also take the one-pair paths.  Integer
+    values keep every sum exact, so both results are bit-exact; two tile rows
+    and columns with ragged edges."""
+    cin, cout = cio
+    r = wl.rng(24, cin, cout, k)
+    shape = (2, cin, 70, 133)
+    x = r.integers(-4, 5, shape).astype(np.float32)
+    f = r.integers(-4, 5, (cout, cin, k, k)).astype(np.float32)
+    g = r.integers(-4, 5, (2, cout, 70, 133)).astype(np.float32)
+    gi, gf = gpu_lib.backward(dev(x), dev(f), dev(g), mode="bank")
+    want_i = oracle.grad_input(g.astype(np.float64), f.astype(np.float64), shape, "bank")
+    want_f = oracle.grad_filter(x.astype(np.float64), g.astype(np.float64), f.shape, "bank")
+    assert np.array_equal(gi.double().cpu().numpy(), want_i)
+    assert np.array_equal(gf.double().cpu().numpy(), want_f)
+
+
 @pytest.mark.parametrize("hw", [(1, 1), (2, 3), (6, 5), (40, 33)])
 def test_adjoint_identity_on_gpu(gpu_lib, hw):
     k = 7
