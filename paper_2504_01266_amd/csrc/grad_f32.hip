@@ -559,11 +559,13 @@ hipError_t launch_grad_filter_f32(const GradFilterParams& p, int K, hipStream_t 
 }
 
 // Filter pairs per work-group of the grouped bank kernel: NO output x NI
-// input channels for K = 1, 3 (4 x 4) and 5 (2 x 2); false where it does not
+// input channels for K = 1, 3 (4 x 2) and 5 (2 x 2); false where it does not
 // apply (other modes or K, or channel counts that the groups do not divide).
+// (4 x 4 at K = 3 staged fewer tiles but held 240 registers, two waves per
+// SIMD: 4% slower than 4 x 2 at three.)
 bool grad_filter_bank_groups(int mode, int K, int64_t co, int64_t ci, int* no, int* ni) {
   *no = K <= 3 ? 4 : 2;
-  *ni = K <= 3 ? 4 : 2;
+  *ni = 2;
   return mode == F2D_CH_BANK && (K == 1 || K == 3 || K == 5) && co % *no == 0 && ci % *ni == 0;
 }
 
@@ -572,8 +574,8 @@ hipError_t launch_grad_filter_bank_f32(const GradFilterParams& p, int K, hipStre
   if (p.n_units <= 0) return hipSuccess;
   const dim3 grid(static_cast<uint32_t>(p.n_units)), block(kThreads);
   switch (K) {
-    case 1: hipLaunchKernelGGL((k_grad_filter_bank_f32<1, 4, 4>), grid, block, 0, s, p); break;
-    case 3: hipLaunchKernelGGL((k_grad_filter_bank_f32<3, 4, 4>), grid, block, 0, s, p); break;
+    case 1: hipLaunchKernelGGL((k_grad_filter_bank_f32<1, 4, 2>), grid, block, 0, s, p); break;
+    case 3: hipLaunchKernelGGL((k_grad_filter_bank_f32<3, 4, 2>), grid, block, 0, s, p); break;
     case 5: hipLaunchKernelGGL((k_grad_filter_bank_f32<5, 2, 2>), grid, block, 0, s, p); break;
     default: return hipErrorInvalidValue;
   }
