@@ -71,7 +71,8 @@ def test_bank_backward_f32_channel_groups(gpu_lib, cio, k):
     """FP32 banks whose channel counts the grouped kernels divide: grad_input
     with four image channels per work-group (C_in % 4 == 0, K <= 5) and
     grad_filter with 4 x 2 (K <= 3) or 2 x 2 (K = 5) filter pairs per
-    work-group; (6, 8) and (4, 6) also take the one-pair paths.  Integer
+    work-group; (6, 8) takes the one-channel grad_input and (4, 6) the
+    one-pair grad_filter at K <= 3.  Integer
     values keep every sum exact, so both results are bit-exact; two tile rows
     and columns with ragged edges."""
     cin, cout = cio
