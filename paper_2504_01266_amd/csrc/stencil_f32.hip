@@ -130,15 +130,28 @@ __global__ __launch_bounds__(kThreads) void k_stencil_f32(StencilParams p) {
     }
     stage_tile<K, PX, PY, ADJ || ZB, NOUT == 1>(lds, sp, sh, p.H, p.W, p.row0 + oy0, ox0);
 
-    float tap[NOUT][K * K];
-#pragma unroll
-    for (int j = 0; j < NOUT; ++j) {
-      const float* fp = filt + static_cast<int64_t>(p.f0 + g * p.fg + j * p.fj + s * p.fs) * (K * K);
-#pragma unroll
-      for (int e = 0; e < K * K; ++e) tap[j][e] = fp[ADJ ? (K * K - 1 - e) : e];
-    }
+    // Taps live in scalar registers; more than 64 of them (four outputs at
+    // K = 5) no longer fit beside the kernel's other scalars, and spilling
+    // them to vector-register lanes costs a lane write and read per tap per
+    // tile, so the forward accumulates those outputs in two passes over the
+    // window, half the outputs each (the same per-output order, so the same
+    // bits; 5x5 bank forward 27.7 -> 26.5 ms).  The adjoint keeps one pass:
+    // split, it needs more vector registers (one wave per SIMD fewer) and
+    // measured slower (5x5 bank backward 61.9 -> 65.4 ms).
+    constexpr int NH = !ADJ && NOUT * K * K > 64 && NOUT % 2 == 0 ? NOUT / 2 : NOUT;
     __syncthreads();
-    accumulate<K, NOUT, PX, PY>(lds, tap, acc);
+#pragma unroll
+    for (int h = 0; h < NOUT / NH; ++h) {
+      float tap[NH][K * K];
+#pragma unroll
+      for (int jj = 0; jj < NH; ++jj) {
+        const int j = h * NH + jj;
+        const float* fp = filt + static_cast<int64_t>(p.f0 + g * p.fg + j * p.fj + s * p.fs) * (K * K);
+#pragma unroll
+        for (int e = 0; e < K * K; ++e) tap[jj][e] = fp[ADJ ? (K * K - 1 - e) : e];
+      }
+      accumulate<K, NH, PX, PY>(lds, tap, *reinterpret_cast<float(*)[NH][PY][PX]>(&acc[h * NH]));
+    }
     __syncthreads();
   }
 
